@@ -1,0 +1,564 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by the
+mathematics (closed forms, exact invariants, analytic solutions).
+
+None of these checks re-types the oracle's formulas: each compares the
+oracle with a property that a mistake (a dropped term, a wrong sign, a
+wrong index or weight) would break.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import CORRECTED, PLAIN, Oracle
+from paper_1405_2232_amd import inputs
+
+EX, EY, W = oracle.velocities()
+
+
+# ---------------------------------------------------------------------------
+# lattice and single-node closed forms
+# ---------------------------------------------------------------------------
+
+def test_velocity_set_isotropy():
+    """D2Q9 moments up to fourth order: sum w = 1, sum w e e = c_s^2 I,
+    sum w e e e e = c_s^4 (delta delta + ...), odd moments vanish."""
+    e = np.stack([EX, EY], 1).astype(float)
+    assert abs(W.sum() - 1) < 1e-15
+    assert np.allclose((W[:, None] * e).sum(0), 0, atol=1e-16)
+    m2 = np.einsum("i,ia,ib->ab", W, e, e)
+    assert np.allclose(m2, np.eye(2) / 3, atol=1e-16)
+    m3 = np.einsum("i,ia,ib,ic->abc", W, e, e, e)
+    assert np.allclose(m3, 0, atol=1e-16)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", W, e, e, e, e)
+    d = np.eye(2)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9.0
+    assert np.allclose(m4, iso, atol=1e-16)
+    # every direction has its opposite
+    for i in range(9):
+        assert any(EX[k] == -EX[i] and EY[k] == -EY[i] for k in range(9))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_feq_moments(seed):
+    """sum feq = rho, sum e feq = rho u, sum e e feq = rho c_s^2 I + rho u u
+    (the equilibrium moments used in Eqs. (16)-(17))."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.01, 2.0)
+    u = rng.uniform(-0.2, 0.2, 2)
+    f = oracle.feq(rho, u[0], u[1])
+    e = np.stack([EX, EY], 1).astype(float)
+    assert abs(f.sum() - rho) < 1e-15 * 10
+    assert np.allclose(e.T @ f, rho * u, atol=1e-15)
+    m2 = np.einsum("i,ia,ib->ab", f, e, e)
+    assert np.allclose(m2, rho / 3 * np.eye(2) + rho * np.outer(u, u), atol=2e-15)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_guo_forcing_moments(seed):
+    """Forcing term moments: sum F_i = 0, sum e F_i = (1 - 1/(2 tau)) F,
+    sum e e F_i = (1 - 1/(2 tau)) (u F + F u)."""
+    rng = np.random.default_rng(100 + seed)
+    tau = rng.uniform(0.55, 2.0)
+    u = rng.uniform(-0.2, 0.2, 2)
+    F = rng.uniform(-0.05, 0.05, 2)
+    Fi = oracle.guo(tau, u[0], u[1], F[0], F[1])
+    e = np.stack([EX, EY], 1).astype(float)
+    k = 1 - 1 / (2 * tau)
+    assert abs(Fi.sum()) < 1e-17
+    assert np.allclose(e.T @ Fi, k * F, atol=1e-17)
+    m2 = np.einsum("i,ia,ib->ab", Fi, e, e)
+    assert np.allclose(m2, k * (np.outer(u, F) + np.outer(F, u)), atol=1e-17)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_correction_term_moments(seed):
+    """Eq. (25) and the three identities stated right after it:
+    sum C_i = 0, sum e C_i = (1 - 0.5/tau_g) cv T F, sum e e C_i = 0."""
+    rng = np.random.default_rng(200 + seed)
+    tau_g = rng.uniform(0.55, 2.0)
+    cvT = rng.uniform(0.01, 3.0)
+    F = rng.uniform(-0.05, 0.05, 2)
+    C = oracle.corr(tau_g, cvT, F[0], F[1])
+    e = np.stack([EX, EY], 1).astype(float)
+    assert abs(C.sum()) < 1e-17
+    assert np.allclose(e.T @ C, (1 - 0.5 / tau_g) * cvT * F, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", C, e, e), 0, atol=1e-17)
+
+
+# ---------------------------------------------------------------------------
+# equation of state
+# ---------------------------------------------------------------------------
+
+def _dp(cfg, rho, T, h=1e-5):
+    return (oracle.pressure(cfg, rho + h, T) - oracle.pressure(cfg, rho - h, T)) / (2 * h)
+
+
+def test_cs_eos_critical_point():
+    """The CS EOS has its critical point at T_c = 0.3773 a/(bR),
+    rho_c = 0.5218/b, p_c = 0.0707 a/b^2 (published constants of this EOS)."""
+    cfg = dict(eos="cs", a=1.0, b=4.0, R=1.0)
+    Tc = 0.3773 / 4.0
+    # at T slightly above T_c, dp/drho > 0 everywhere; slightly below, it dips negative
+    rhos = np.linspace(0.05, 0.25, 4001)
+    above = min(_dp(cfg, r, Tc * 1.001) for r in rhos)
+    below = min(_dp(cfg, r, Tc * 0.999) for r in rhos)
+    assert above > 0 > below
+    # inflection with zero slope near rho_c
+    dps = np.array([_dp(cfg, r, Tc) for r in rhos])
+    rc = rhos[np.argmin(dps)]
+    assert abs(rc - 0.5218 / 4) < 5e-4
+    # the published constants carry three to four digits
+    assert abs(oracle.pressure(cfg, 0.5218 / 4, Tc) * 16 - 0.0707) < 1e-4
+
+
+def test_eos_low_density_virial_and_ideal():
+    """Low-density limit of CS: p = rho R T + (b R T - a) rho^2 + O(rho^3);
+    the ideal EOS of Section III is p = rho R T."""
+    cfg = dict(eos="cs", a=1.0, b=4.0, R=1.0)
+    T = 0.07
+    for rho in (1e-4, 2e-4):
+        p = oracle.pressure(cfg, rho, T)
+        B2 = (p - rho * T) / rho ** 2
+        assert abs(B2 - (4.0 * T - 1.0)) < 1e-2 * abs(4.0 * T - 1.0) + 30 * rho
+    ideal = dict(eos="ideal", R=0.5)
+    assert oracle.pressure(ideal, 0.7, 1.3) == pytest.approx(0.7 * 0.5 * 1.3, rel=1e-15)
+
+
+def test_maxwell_construction_equal_area():
+    """The input generator's coexistence densities: equal pressure and equal
+    area, integral of (p - p_s) d(1/rho) = 0."""
+    from scipy.integrate import quad
+    cfg = dict(eos="cs", a=1.0, b=4.0, R=1.0)
+    for ratio in (0.7, 0.85, 0.95):
+        T = ratio * inputs.cs_tc()
+        rv, rl = inputs.maxwell_densities(T)
+        pv, pl = oracle.pressure(cfg, rv, T), oracle.pressure(cfg, rl, T)
+        assert abs(pv - pl) < 1e-12
+        area, _ = quad(lambda r: (oracle.pressure(cfg, r, T) - pv) / r ** 2, rv, rl,
+                       epsabs=1e-14, epsrel=1e-12, limit=200)
+        assert abs(area) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# pseudopotential force
+# ---------------------------------------------------------------------------
+
+def _poly_fields(n, rng):
+    """Random polynomial of total degree 4 and its first derivatives and
+    gradient of the Laplacian, sampled on an n x n grid."""
+    c = rng.uniform(-1, 1, (5, 5)) * 1e-3
+    for i in range(5):
+        for j in range(5):
+            if i + j > 4:
+                c[i, j] = 0
+    x = np.arange(n, dtype=float)[None, :] - n / 2
+    y = np.arange(n, dtype=float)[:, None] - n / 2
+
+    def P(dx=0, dy=0):
+        out = np.zeros((n, n))
+        for i in range(5):
+            for j in range(5):
+                if c[i, j] == 0 or i < dx or j < dy:
+                    continue
+                k = c[i, j] * math.perm(i, dx) * math.perm(j, dy)
+                out = out + k * x ** (i - dx) * y ** (j - dy)
+        return out
+
+    val = P() + 1.0
+    gx, gy = P(1, 0), P(0, 1)
+    glx = P(3, 0) + P(1, 2)
+    gly = P(2, 1) + P(0, 3)
+    return val, gx, gy, glx, gly
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_force_stencil_taylor_exact_for_quartics(seed):
+    """Eq. (3): sum_i w psi(x+e_i) e_i = grad psi + (1/6) grad lap psi with
+    no remainder for polynomials of degree <= 4 (the fifth-order lattice
+    moments vanish), for both the Eq. (2) and the beta = 0 forms of Eq. (4)."""
+    rng = np.random.default_rng(seed)
+    n = 16
+    psi, gx, gy, glx, gly = _poly_fields(n, rng)
+    G = -1.0
+    sl = (slice(2, n - 2), slice(2, n - 2))
+    # Eq. (2): F = -G psi (grad psi + grad lap psi / 6)
+    Fx, Fy = oracle.sc_force_field(psi, psi ** 2, G, beta=1.0)
+    assert np.allclose(Fx[sl], -G * psi[sl] * (gx[sl] + glx[sl] / 6), atol=1e-13, rtol=0)
+    assert np.allclose(Fy[sl], -G * psi[sl] * (gy[sl] + gly[sl] / 6), atol=1e-13, rtol=0)
+    # beta = 0: F = -G/2 sum w psi^2(x+e) e, with psi^2 a quartic
+    Fx, Fy = oracle.sc_force_field(np.zeros_like(psi), psi, G, beta=0.0)
+    assert np.allclose(Fx[sl], -0.5 * G * (gx[sl] + glx[sl] / 6), atol=1e-13, rtol=0)
+    assert np.allclose(Fy[sl], -0.5 * G * (gy[sl] + gly[sl] / 6), atol=1e-13, rtol=0)
+
+
+def test_force_wall_mirror_ghost():
+    """At a wall the ghost node beyond it takes the boundary node's psi, so
+    a field uniform along the wall normal feels no normal force at the wall."""
+    n = 8
+    psi = np.tile(np.linspace(1, 2, n)[None, :], (n, 1))  # varies in x only
+    Fx, Fy = oracle.sc_force_field(psi, psi ** 2, -1.0, wall_y=True)
+    assert np.allclose(Fy, 0, atol=1e-16)
+    # along x with walls: boundary column sees itself as the outer neighbour
+    Fx, Fy = oracle.sc_force_field(psi, psi ** 2, -1.0, wall_x=True)
+    x0 = (1 / 3) * (psi[0, 1] - psi[0, 0]) + 2 * (1 / 12) * (psi[0, 1] - psi[0, 0])
+    assert Fx[3, 0] == pytest.approx(psi[0, 0] * x0, rel=1e-14)
+
+
+def test_force_long_wave_limit():
+    """Below Eq. (4): F ~ -grad(p_EOS - rho c_s^2) for smooth fields, with
+    an error that falls as the square of the wavenumber."""
+    T0 = 0.9 * inputs.cs_tc()
+    errs = []
+    for n in (64, 128):
+        p = inputs.base_params(n, 4, T0)
+        p["eos_fixed_T"] = True
+        x = np.arange(n)
+        rho1 = 0.12 + 0.02 * np.sin(2 * np.pi * x / n)
+        rho = np.tile(rho1[None, :], (4, 1))
+        o = Oracle(p)
+        o.init_fields(rho, np.full_like(rho, T0))
+        Fx, Fy = o.force()
+        h = 1e-6
+        dp = np.array([(oracle.pressure(p, r + h, T0) - (r + h) / 3
+                        - oracle.pressure(p, r - h, T0) + (r - h) / 3) / (2 * h) for r in rho1])
+        drho = 0.02 * 2 * np.pi / n * np.cos(2 * np.pi * x / n)
+        exact = -dp * drho
+        errs.append(np.abs(Fx[0] - exact).max() / np.abs(exact).max())
+        assert np.abs(Fy).max() < 1e-15
+    order = math.log(errs[0] / errs[1], 2)
+    assert errs[1] < 2e-3
+    assert 1.8 < order < 2.3, (errs, order)
+
+
+def test_pseudopotential_momentum_sums_to_zero():
+    """Pairwise antisymmetry of Eq. (2): the net pseudopotential force over
+    a periodic domain vanishes for any field."""
+    p, rho, T = inputs.static_droplet(nx=48, ny=40, radius=10)
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    Fx, Fy = o.force()
+    scale = np.abs(Fx).sum() + np.abs(Fy).sum()
+    assert abs(Fx.sum()) < 1e-14 * scale
+    assert abs(Fy.sum()) < 1e-14 * scale
+
+
+# ---------------------------------------------------------------------------
+# full-step invariants
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("treatment", [PLAIN, CORRECTED])
+def test_mass_and_energy_conserved_periodic(treatment):
+    """Collision conserves sum f and sum g (sum C_i = 0 for the corrected
+    equation), streaming moves them: totals stay fixed to rounding."""
+    p, rho, T = inputs.static_droplet()
+    p["eos_fixed_T"] = True
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    t0 = o.totals()
+    assert o.step(1000, treatment) == 0
+    t1 = o.totals()
+    assert abs(t1[0] - t0[0]) < 1e-12 * t0[0]
+    assert abs(t1[1] - t0[1]) < 1e-12 * t0[1]
+    assert t1[6] == 1000
+
+
+def test_mass_conserved_with_bounce_back_walls():
+    p, rho, T = inputs.wall_slab(nx=4, ny=64)
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    m0 = o.totals()[0]
+    assert o.step(500, CORRECTED) == 0
+    assert abs(o.totals()[0] - m0) < 1e-12 * m0
+
+
+def test_momentum_budget_with_gravity():
+    """With Guo forcing, sum_i e_i f_i gains exactly F per node per step; the
+    pseudopotential part sums to zero, so the total gains g * sum rho."""
+    p, rho, T = inputs.static_droplet(nx=40, ny=40, radius=9)
+    p["gx"], p["gy"] = 2e-5, -3e-5
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    for _ in range(5):
+        f, _ = o.get_state()
+        jx0, jy0 = (f * EX[:, None, None]).sum(), (f * EY[:, None, None]).sum()
+        mass = f.sum()
+        o.step(1, CORRECTED)
+        f1, _ = o.get_state()
+        jx1, jy1 = (f1 * EX[:, None, None]).sum(), (f1 * EY[:, None, None]).sum()
+        assert jx1 - jx0 == pytest.approx(p["gx"] * mass, rel=1e-9, abs=1e-15)
+        assert jy1 - jy0 == pytest.approx(p["gy"] * mass, rel=1e-9, abs=1e-15)
+
+
+def _rotate_ccw(a):
+    """Rotate a field on a periodic N x N lattice by 90 degrees about the
+    origin node: (x, y) -> (-y mod N, x)."""
+    n = a.shape[0]
+    out = np.empty_like(a)
+    for y in range(n):
+        for x in range(n):
+            out[x, (-y) % n] = a[y, x]
+    return out
+
+
+def _mirror_x(a):
+    n = a.shape[1]
+    out = np.empty_like(a)
+    for x in range(n):
+        out[:, (-x) % n] = a[:, x]
+    return out
+
+
+@pytest.mark.parametrize("treatment", [PLAIN, CORRECTED])
+def test_rotation_and_mirror_covariance(treatment):
+    """The scheme commutes with the lattice symmetries: rotating (or
+    mirroring) the initial state rotates (mirrors) the state 25 steps later."""
+    n = 24
+    p, rho, T = inputs.static_droplet(nx=n, ny=n, radius=6, seed=7)
+    p["eos_fixed_T"] = True
+    rng = np.random.default_rng(3)
+    ux = rng.uniform(-0.01, 0.01, (n, n))
+    uy = rng.uniform(-0.01, 0.01, (n, n))
+
+    def run(r, t, u, v):
+        o = Oracle(p)
+        o.init_fields(r, t, u, v)
+        o.step(25, treatment)
+        return o.moments()
+
+    base = run(rho, T, ux, uy)
+    # rotation: velocity (u, v) -> (-v, u)
+    rot = run(_rotate_ccw(rho), _rotate_ccw(T), -_rotate_ccw(uy), _rotate_ccw(ux))
+    assert np.allclose(rot[0], _rotate_ccw(base[0]), rtol=0, atol=1e-13)
+    assert np.allclose(rot[1], -_rotate_ccw(base[2]), rtol=0, atol=1e-13)
+    assert np.allclose(rot[2], _rotate_ccw(base[1]), rtol=0, atol=1e-13)
+    assert np.allclose(rot[3], _rotate_ccw(base[3]), rtol=0, atol=1e-13)
+    # mirror in x: (u, v) -> (-u, v)
+    mir = run(_mirror_x(rho), _mirror_x(T), -_mirror_x(ux), _mirror_x(uy))
+    assert np.allclose(mir[0], _mirror_x(base[0]), rtol=0, atol=1e-13)
+    assert np.allclose(mir[1], -_mirror_x(base[1]), rtol=0, atol=1e-13)
+    assert np.allclose(mir[2], _mirror_x(base[2]), rtol=0, atol=1e-13)
+    assert np.allclose(mir[3], _mirror_x(base[3]), rtol=0, atol=1e-13)
+
+
+def test_init_returns_fields_single_phase():
+    """With no force, initialising at equilibrium returns rho, u, T."""
+    n = 12
+    rng = np.random.default_rng(5)
+    p = inputs.base_params(n, n, 0.08)
+    p["G"] = 0.0
+    rho = rng.uniform(0.5, 1.5, (n, n))
+    ux = rng.uniform(-0.05, 0.05, (n, n))
+    uy = rng.uniform(-0.05, 0.05, (n, n))
+    T = rng.uniform(0.5, 1.5, (n, n))
+    o = Oracle(p)
+    o.init_fields(rho, T, ux, uy)
+    r, u, v, t = o.moments()
+    assert np.allclose(r, rho, rtol=1e-15, atol=0)
+    assert np.allclose(u, ux, rtol=0, atol=1e-16)
+    assert np.allclose(v, uy, rtol=0, atol=1e-16)
+    assert np.allclose(t, T, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# single-phase analytic solutions (G = 0): textbook BGK and advection-diffusion
+# ---------------------------------------------------------------------------
+
+def _shear_rate(tau_f, ny):
+    p = inputs.base_params(2, ny, 1.0, tau_f=tau_f)
+    p["G"] = 0.0
+    y = np.arange(ny)
+    k = 2 * np.pi / ny
+    ux = np.tile((1e-4 * np.sin(k * y))[:, None], (1, 2))
+    o = Oracle(p)
+    o.init_fields(np.ones((ny, 2)), np.ones((ny, 2)), ux, np.zeros((ny, 2)))
+    o.step(ny, PLAIN)
+    a0 = np.abs(o.moments()[1]).max()
+    t = int(0.4 / ((tau_f - 0.5) / 3 * k * k))
+    o.step(t, PLAIN)
+    a1 = np.abs(o.moments()[1]).max()
+    return -math.log(a1 / a0) / (k * k * t)
+
+
+@pytest.mark.parametrize("tau_f", [0.6, 1.0, 1.5])
+def test_shear_wave_decay_viscosity(tau_f):
+    """A sinusoidal shear wave decays at nu k^2, nu = (tau_f - 1/2) c_s^2;
+    the lattice correction to the rate falls at second order in k."""
+    nu = (tau_f - 0.5) / 3
+    e1 = abs(_shear_rate(tau_f, 32) / nu - 1)
+    e2 = abs(_shear_rate(tau_f, 64) / nu - 1)
+    assert e2 < 1e-2
+    assert e2 < 1e-6 or 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+def _gauss_run(n, sigma0, tau_g, t):
+    p = inputs.base_params(n, n, 1.0, tau_g=tau_g)
+    p["G"] = 0.0
+    x = np.arange(n)[None, :] - n / 2
+    y = np.arange(n)[:, None] - n / 2
+    r2 = x ** 2 + y ** 2
+    A = 0.1
+    T0 = 1.0 + A * np.exp(-r2 / (2 * sigma0 ** 2))
+    o = Oracle(p)
+    o.init_fields(np.ones((n, n)), T0)
+    o.step(t, PLAIN)
+    chi = (tau_g - 0.5) / 3
+    s2 = sigma0 ** 2 + 2 * chi * t
+    exact = 1.0 + A * sigma0 ** 2 / s2 * np.exp(-r2 / (2 * s2))
+    return np.abs(o.moments()[3] - exact).max() / A
+
+
+@pytest.mark.parametrize("tau_g", [0.8, 1.2])
+def test_gaussian_diffusion_second_order(tau_g):
+    """Single phase at rest: Eq. (7) diffuses T with chi = (tau_g - 1/2) c_s^2
+    (lambda/(rho cv) of Eq. (23) with F = 0); the error against the Gaussian
+    solution falls at second order under diffusive refinement."""
+    chi = (tau_g - 0.5) / 3
+    t1 = int(round(16.0 / chi))
+    e1 = _gauss_run(64, 4.0, tau_g, t1)
+    e2 = _gauss_run(128, 8.0, tau_g, 4 * t1)
+    order = math.log(e1 / e2, 2)
+    assert e2 < 1e-3
+    assert 1.8 < order < 2.2, (e1, e2, order)
+
+
+@pytest.mark.parametrize("tau_g", [0.6, 0.8, 1.2])
+def test_linear_conduction_between_dirichlet_walls(tau_g):
+    """Steady conduction between walls at T_b (y = -1/2) and T_t
+    (y = ny - 1/2): T is exactly linear in y."""
+    ny = 16
+    p = inputs.base_params(2, ny, 1.0, tau_g=tau_g)
+    p.update(G=0.0, wall_y=True, thermal_bottom="dirichlet", thermal_top="dirichlet",
+             T_bottom=0.9, T_top=1.1)
+    o = Oracle(p)
+    o.init_fields(np.ones((ny, 2)), np.ones((ny, 2)))
+    chi = (tau_g - 0.5) / 3
+    o.step(int(40 / (chi * (math.pi / ny) ** 2)), PLAIN)
+    T = o.moments()[3]
+    y = np.arange(ny)
+    exact = 0.9 + 0.2 * (y + 0.5) / ny
+    assert np.abs(T - exact[:, None]).max() < 1e-12
+
+
+def test_adiabatic_walls_conserve_energy():
+    ny = 16
+    p = inputs.base_params(3, ny, 1.0)
+    p.update(G=0.0, wall_y=True, thermal_bottom="adiabatic", thermal_top="adiabatic")
+    T0 = np.tile((1.0 + 0.1 * np.cos(np.pi * (np.arange(ny) + 0.5) / ny))[:, None], (1, 3))
+    o = Oracle(p)
+    o.init_fields(np.ones((ny, 3)), T0)
+    e0 = o.totals()[1]
+    o.step(20000, PLAIN)
+    T = o.moments()[3]
+    assert abs(o.totals()[1] - e0) < 1e-12 * e0
+    assert np.abs(T - T0.mean()).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the forcing-term effect (Eq. (23) vs. Eq. (A11))
+# ---------------------------------------------------------------------------
+
+def _slab_steady(treatment, tau_g, steps=40000):
+    p, rho, T = inputs.wall_slab(nx=2, ny=64)
+    p.update(wall_y=False, eos_fixed_T=True, tau_g=tau_g)
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    assert o.step(steps, treatment) == 0
+    return o.moments()
+
+
+@pytest.mark.parametrize("tau_g", [1.0, 0.8])
+def test_slab_steady_state_forcing_term_effect(tau_g):
+    """Flat two-phase slab at mechanical equilibrium (u = 0), EOS at a fixed
+    temperature.  Eq. (23) with a zero total flux, lambda grad T + theta T F
+    = (tau_g - 1/2) cv grad(p T) with F = grad p, makes rho T uniform for the
+    plain equation (7); Eq. (A11) makes T uniform for the corrected Eq. (24)."""
+    rho, ux, uy, T = _slab_steady(PLAIN, tau_g)
+    assert np.abs(ux).max() < 1e-13 and np.abs(uy).max() < 1e-13
+    rT = rho * T
+    assert (rT.max() - rT.min()) / rT.mean() < 1e-10
+    # the temperature jump follows the density ratio
+    assert T.max() / T.min() == pytest.approx(rho.max() / rho.min(), rel=1e-9)
+    assert rho.max() / rho.min() > 5
+    rho_c, _, _, T_c = _slab_steady(CORRECTED, tau_g)
+    assert (T_c.max() - T_c.min()) / T_c.mean() < 1e-10
+
+
+def _smooth_state(n, k_mult=1):
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    k = 2 * np.pi * k_mult / n
+    rho = 0.12 + 0.03 * np.sin(k * x) * np.cos(k * y)
+    T = 0.08 * (1 + 0.05 * np.cos(k * x + 0.3)) * np.ones((n, 1))
+    return rho, T
+
+
+def test_one_step_treatment_gap_is_divergence_of_correction_flux():
+    """From one state, the corrected minus plain energy after one step is
+    the streamed C_i, whose leading order is -div((1 - 1/(2 tau_g)) cv T F)
+    (the divergence of the first moment of Eq. (25)); the remainder falls
+    at second order."""
+    errs = []
+    for n in (32, 64):
+        p = inputs.base_params(n, n, 0.08)
+        p["eos_fixed_T"] = True
+        rho, T = _smooth_state(n)
+        res = {}
+        for tr in (PLAIN, CORRECTED):
+            o = Oracle(p)
+            o.init_fields(rho, T)
+            Fx, Fy = o.force()
+            o.step(1, tr)
+            _, g = o.get_state()
+            res[tr] = g.sum(0)
+        gap = res[CORRECTED] - res[PLAIN]
+        k = 1 - 1 / (2 * p["tau_g"])
+        qx, qy = k * T * Fx, k * T * Fy
+        # spectral divergence of the smooth flux
+        kx = 2 * np.pi * np.fft.fftfreq(n)
+        div = np.real(np.fft.ifft(1j * kx[None, :] * np.fft.fft(qx, axis=1), axis=1)
+                      + np.fft.ifft(1j * kx[:, None] * np.fft.fft(qy, axis=0), axis=0))
+        errs.append(np.abs(gap + div).max() / np.abs(div).max())
+    order = math.log(errs[0] / errs[1], 2)
+    assert errs[1] < 0.02
+    assert 1.7 < order < 2.4, (errs, order)
+
+
+# ---------------------------------------------------------------------------
+# EOS domain
+# ---------------------------------------------------------------------------
+
+def test_psi_domain_clamp_counted_and_policy():
+    """psi^2 < 0 (hot vapour with G = -1 needs p_EOS <= rho/3) clamps psi
+    to zero and is counted; the strict policy stops with a domain error."""
+    n = 16
+    p = inputs.base_params(n, n, 0.08)
+    rho = np.full((n, n), 0.03)
+    T = np.full((n, n), 0.08)
+    T[4:8, 4:8] = 0.5  # p = rho R T (...) > rho/3 there
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    assert o.step(1, CORRECTED) == 0
+    assert o.totals()[5] >= 16
+    p["psi_policy"] = 1
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    assert o.step(5, CORRECTED) == -5
+    assert o.totals()[6] == 1
+
+
+def test_plain_treatment_leaves_eos_domain_when_coupled():
+    """Reading of the droplet workload: with the EOS at the local temperature,
+    the plain Eq. (7) heats the vapour beyond the real-psi domain within
+    40 steps, while the corrected Eq. (24) stays inside it."""
+    p, rho, T = inputs.static_droplet()
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    o.step(40, PLAIN)
+    assert o.totals()[5] > 0
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    o.step(400, CORRECTED)
+    assert o.totals()[5] == 0
