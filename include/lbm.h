@@ -1,0 +1,187 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the
+ * double-distribution-function pseudopotential thermal lattice Boltzmann
+ * step of Li & Luo, "Effect of the forcing term in the pseudopotential
+ * lattice Boltzmann modeling of thermal flows" (arXiv:1405.2232).
+ *
+ * One time step (lbm_step) on a D2Q9 lattice of nx * ny nodes is:
+ *   - moments rho = sum f_i, j = sum e_i f_i, rho cv T = sum g_i;
+ *   - pseudopotential psi = sqrt(2 (p_EOS - rho c_s^2)/(G c^2))
+ *     (Section II.A) for the node and its eight neighbours;
+ *   - the pseudopotential force of Eq. (2), or its mixed form Eq. (4),
+ *     plus a body force rho (gx, gy) (the buoyancy of Section III.B);
+ *   - BGK collision of f with the forcing term F_i, Eq. (1), with the
+ *     velocity u = (j + F/2)/rho;
+ *   - BGK collision of g with g^eq = cv T f^eq, Eq. (7) (LBM_PLAIN), or
+ *     the corrected Eq. (24) with the correction term C_i of Eq. (25)
+ *     (LBM_CORRECTED);
+ *   - streaming, with periodic wrap or halfway bounce-back walls.
+ *
+ * Conventions
+ *   - Host arrays are FP64, row-major [ny][nx] with x fastest.
+ *   - Device memory is owned by the caller: lbm_workspace_bytes() says how
+ *     much, lbm_create() borrows it (it must outlive lbm_destroy()).  The
+ *     library allocates no device memory of its own.
+ *   - All device work is enqueued on the HIP stream given to lbm_create()
+ *     (a hipStream_t passed as void*; NULL is the null stream).
+ *   - Every function returns an int status (LBM_OK or a negative code);
+ *     no C++ exception crosses this boundary.  Asynchronous device faults
+ *     surface as LBM_EDEVICE from the next call that synchronizes.
+ *   - Calls on one handle must not overlap (not thread-safe per handle).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument or parameter */
+  LBM_ENOMEM = -2,     /* workspace too small */
+  LBM_EDEVICE = -3,    /* HIP runtime error */
+  LBM_ENONFINITE = -4, /* a density or energy became NaN/Inf */
+  LBM_EDOMAIN = -5,    /* psi^2 < 0 met under the strict psi policy */
+  LBM_ESTATE = -6      /* call out of order (e.g. step before init) */
+};
+
+/* temperature treatments */
+enum {
+  LBM_PLAIN = 0,    /* Eq. (7): carries the forcing-term effect of Eq. (23) */
+  LBM_CORRECTED = 1 /* Eq. (24) with C_i of Eq. (25): recovers Eq. (A11) */
+};
+
+/* storage precision of the distributions */
+enum {
+  LBM_FP64 = 0,      /* f_i, g_i stored and updated in FP64 */
+  LBM_FP32_DEV = 1,  /* stored in FP32 as deviations f_i - w_i rho_ref and
+                        g_i - w_i rho_ref cv T_ref (global shifts); the
+                        collision runs in FP32; moments, EOS, psi, force and
+                        reductions in FP64 */
+  LBM_FP32_LOCAL = 2 /* as LBM_FP32_DEV, but the density shift is per node:
+                        f_i - w_i rho_bar(x), g_i - w_i rho_bar(x) cv T_ref,
+                        rho_bar(x) the node's density one step earlier
+                        rounded to FP16 and stored beside the distributions
+                        (2 more bytes per node and copy) */
+};
+
+enum { LBM_EOS_CS = 0, LBM_EOS_IDEAL = 1 };
+enum { LBM_THERMAL_DIRICHLET = 0, LBM_THERMAL_ADIABATIC = 1 };
+
+typedef struct {
+  int nx, ny;           /* lattice nodes; 1 <= nx, ny; nx*ny < 2^31, and
+                           the nine f (or g) planes of one copy below
+                           4 GiB (about 7,400^2 nodes in FP64) */
+  double tau_f, tau_g;  /* relaxation times of Eq. (1) and Eq. (7); > 0.5 */
+  double G;             /* interaction strength of Eq. (2); 0 disables it */
+  double beta;          /* Eq. (4) mixing weight; 1 gives Eq. (2) */
+  int eos;              /* LBM_EOS_CS: Carnahan-Starling,
+                           p = rho R T (1+e+e^2-e^3)/(1-e)^3 - a rho^2,
+                           e = b rho/4; LBM_EOS_IDEAL: p = rho R T
+                           (the EOS of Section III) */
+  double a, b, R;       /* EOS constants */
+  int eos_fixed_T;      /* 0: EOS at the local T (coupled); 1: at T_eos */
+  double T_eos;
+  double cv;            /* specific heat in g^eq = cv T f^eq; > 0 */
+  double gx, gy;        /* body acceleration; force rho * (gx, gy) */
+  int wall_x, wall_y;   /* 0: periodic; 1: walls halfway outside the
+                           first and last node (f bounces back; the psi
+                           ghost mirrors the boundary node) */
+  int thermal_left, thermal_right, thermal_bottom, thermal_top;
+                        /* LBM_THERMAL_DIRICHLET: g anti-bounces back
+                           with the wall value rho cv T_w; ADIABATIC: g
+                           bounces back.  Where a diagonal leaves through
+                           a corner the y wall's condition applies. */
+  double T_left, T_right, T_bottom, T_top;
+  int psi_policy;       /* 0: psi^2 < 0 clamps psi to 0 and is counted;
+                           1: the same, and lbm_sync()/lbm_moments()
+                           return LBM_EDOMAIN once any clamp happened */
+  int precision;        /* LBM_FP64, LBM_FP32_DEV or LBM_FP32_LOCAL */
+  double rho_ref, T_ref;/* deviation shifts: rho_ref for LBM_FP32_DEV,
+                           T_ref for both FP32 forms */
+} lbm_params;
+
+typedef struct lbm_ctx *lbm_handle;
+
+/* Device bytes lbm_create() needs for these parameters. */
+int lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
+
+/* Validate p and bind a caller-owned device workspace of `bytes` bytes
+ * (256-byte aligned) and a HIP stream.  No kernel runs here. */
+int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+               lbm_handle *out);
+
+/* Initialise f_i = f_i^eq(rho, u) and g_i = cv T f_i^eq(rho, u) from host
+ * arrays (ux, uy may be NULL for zero).  Copies are stream-ordered; the
+ * call returns once the host arrays may be reused. */
+int lbm_init_fields(lbm_handle h, const double *rho, const double *ux, const double *uy,
+                    const double *T);
+
+/* Enqueue n >= 1 time steps with the given treatment (it may change from
+ * call to call).  Does not synchronize unless a check interval is set
+ * (lbm_set_check_interval), in which case the status of the last check
+ * is returned. */
+int lbm_step(lbm_handle h, int n, int treatment);
+
+/* Check non-finite moments and the psi policy every k steps inside
+ * lbm_step (k = 0, the default, checks only in lbm_sync / lbm_moments /
+ * lbm_totals). */
+int lbm_set_check_interval(lbm_handle h, int k);
+
+/* Synchronize the stream and report LBM_ENONFINITE / LBM_EDOMAIN /
+ * LBM_EDEVICE. */
+int lbm_sync(lbm_handle h);
+
+/* rho, u = (j + F/2)/rho and T at the current time, to host arrays (any
+ * may be NULL).  Synchronizes. */
+int lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T);
+
+/* The same fields written to caller-owned device arrays of nx*ny doubles
+ * (any may be NULL).  Stream-ordered; does not synchronize. */
+int lbm_moments_device(lbm_handle h, double *d_rho, double *d_ux, double *d_uy, double *d_T);
+
+/* FP64 totals at the current time: out[0] mass sum rho, out[1] energy
+ * sum rho cv T, out[2..3] momentum sum (j + F/2), out[4] number of nodes
+ * with non-finite rho or energy, out[5] psi clamps so far, out[6] steps
+ * taken, out[7] 0.  Synchronizes. */
+int lbm_totals(lbm_handle h, double out[8]);
+
+/* Relative change of rho and T over one step,
+ * max over {rho, T} of ||phi^n - phi^(n-1)||_inf / ||phi^n||_inf.
+ * Takes one step with `treatment`.  Synchronizes. */
+int lbm_step_residual(lbm_handle h, int treatment, double *residual);
+
+/* Raw state, 18 planes [q][ny][nx] (q < 9: f, else g) in FP64 on the host,
+ * deviations added back for LBM_FP32_DEV.  Synchronizes. */
+int lbm_get_state(lbm_handle h, double *state);
+int lbm_set_state(lbm_handle h, const double *state);
+
+/* Checkpoint: write the stored state (raw bytes, any precision), the step
+ * count and the clamp count to `path`; lbm_load restores it into a handle
+ * created with the same parameters, so that a resumed run is bitwise equal
+ * to an uninterrupted one.  LBM_EINVAL on I/O errors or a mismatch. */
+int lbm_save(lbm_handle h, const char *path);
+int lbm_load(lbm_handle h, const char *path);
+
+/* Tile shape of the step kernel: bx columns per block (64, 128 or 256)
+ * and `rows` rows per block (>= 1).  The default comes from the lattice
+ * size; an autotuner may pick another.  Results do not depend on it. */
+int lbm_set_tiling(lbm_handle h, int bx, int rows);
+int lbm_get_tiling(lbm_handle h, int *bx, int *rows);
+
+int lbm_destroy(lbm_handle h);
+const char *lbm_strerror(int status);
+
+/* Measurement aid: copy `bytes` (multiple of 16) from src to dst with a
+ * plain streaming kernel on `hip_stream`; gives the practical HBM
+ * bandwidth ceiling and the copy used to scale byte counters. */
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

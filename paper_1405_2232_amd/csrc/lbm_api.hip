@@ -1,0 +1,585 @@
+// Host side of the liblbm C ABI (include/lbm.h): parameter checks,
+// workspace carving, stream-ordered launches and status reporting.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+using lbmdev::Model;
+using lbmdev::Tiling;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  int pitch;
+  long long plane;        // elements
+  size_t elem;            // bytes per stored value
+  size_t dist_bytes;      // one buffer of 18 planes
+  size_t off_buf[2];
+  size_t off_staging;     // 4 dense FP64 planes
+  size_t off_snap;        // 2 dense FP64 planes
+  size_t off_partials;
+  int max_blocks;
+  size_t off_out;         // kPartials doubles
+  size_t off_counters;    // 8 u64
+  size_t total;
+};
+
+long long env_ll(const char *name, long long dflt);
+
+// Default tile shape: wide strips (inner width bx - 2), bands tall enough
+// that the two halo rows per band stay a small fraction of the loads, and
+// enough blocks to keep every compute unit busy.
+Tiling default_tiling(int nx, int ny, int precision) {
+  Tiling t;
+  t.bx = nx >= 192 ? 256 : (nx > 62 ? 128 : 64);
+  t.strips = (nx + t.bx - 3) / (t.bx - 2);
+  const int target = 1024;
+  int bands = target / t.strips;
+  if (bands < 1) bands = 1;
+  int rows = (ny + bands - 1) / bands;
+  if (rows < 16) rows = 16;
+  if (rows > ny) rows = ny;
+  t.rows = rows;
+  t.bands = (ny + rows - 1) / rows;
+  t.xcd = 1;
+  t.alt = 1;
+  t.nt = 0;
+  t.pf = precision == LBM_FP64 ? 1 : 2;
+  // experiment knobs (environment) override the defaults
+  const long long ebx = env_ll("LBM_BX", 0), erows = env_ll("LBM_ROWS", 0);
+  if (ebx == 64 || ebx == 128 || ebx == 256) t.bx = (int)ebx;
+  if (erows >= 1) t.rows = (int)(erows < ny ? erows : ny);
+  t.strips = (nx + t.bx - 3) / (t.bx - 2);
+  t.bands = (ny + t.rows - 1) / t.rows;
+  t.xcd = (int)env_ll("LBM_XCD", t.xcd);
+  t.alt = (int)env_ll("LBM_ALT", t.alt);
+  t.nt = (int)env_ll("LBM_NT", t.nt);
+  t.pf = (int)env_ll("LBM_PF", t.pf);
+  return t;
+}
+
+long long env_ll(const char *name, long long dflt) {
+  const char *s = getenv(name);
+  if (!s || !*s) return dflt;
+  return atoll(s);
+}
+
+int storage_of(const lbm_params *p) {
+  return p->precision == LBM_FP64 ? lbmdev::ST_F64
+         : (p->precision == LBM_FP32_DEV ? lbmdev::ST_F32_GLOBAL : lbmdev::ST_F32_LOCAL);
+}
+
+bool compute_layout(const lbm_params *p, Layout *L) {
+  const int fp32 = p->precision != LBM_FP64;
+  L->elem = fp32 ? 4 : 8;
+  const int align_elems = (int)(kAlign / L->elem);
+  L->pitch = (int)align_up((size_t)p->nx, (size_t)align_elems);
+  const long long pad = env_ll("LBM_PLANE_PAD", 0);
+  L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) +
+             (pad > 0 ? pad * align_elems : 0);
+  // 18 planes, then (LBM_FP32_LOCAL) one FP16 reference plane
+  L->dist_bytes = align_up((size_t)L->plane * 18 * L->elem +
+                               (p->precision == LBM_FP32_LOCAL ? (size_t)L->plane * 2 : 0),
+                           kAlign);
+  const size_t n = (size_t)p->nx * (size_t)p->ny;
+  size_t off = 0;
+  L->off_buf[0] = off;
+  off += L->dist_bytes;
+  L->off_buf[1] = off;
+  off += L->dist_bytes;
+  L->off_staging = off;
+  off += align_up(4 * n * sizeof(double), kAlign);
+  L->off_snap = off;
+  off += align_up(2 * n * sizeof(double), kAlign);
+  Tiling t = default_tiling(p->nx, p->ny, p->precision);
+  L->max_blocks = t.strips * t.bands;
+  L->off_partials = off;
+  off += align_up((size_t)L->max_blocks * lbmdev::kPartials * sizeof(double), kAlign);
+  L->off_out = off;
+  off += align_up(lbmdev::kPartials * sizeof(double), kAlign);
+  L->off_counters = off;
+  off += align_up(8 * sizeof(unsigned long long), kAlign);
+  L->total = off;
+  return true;
+}
+
+int validate(const lbm_params *p) {
+  if (!p) return LBM_EINVAL;
+  if (p->nx < 1 || p->ny < 1) return LBM_EINVAL;
+  if ((long long)p->nx * p->ny >= (1LL << 31)) return LBM_EINVAL;
+  if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5) || !isfinite(p->tau_f) || !isfinite(p->tau_g))
+    return LBM_EINVAL;
+  if (!(p->cv > 0.0) || !isfinite(p->cv)) return LBM_EINVAL;
+  if (!isfinite(p->G) || !isfinite(p->beta)) return LBM_EINVAL;
+  if (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_IDEAL) return LBM_EINVAL;
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32_DEV && p->precision != LBM_FP32_LOCAL)
+    return LBM_EINVAL;
+  if (p->precision != LBM_FP64 && (!isfinite(p->rho_ref) || !isfinite(p->T_ref))) return LBM_EINVAL;
+  const int th[4] = {p->thermal_left, p->thermal_right, p->thermal_bottom, p->thermal_top};
+  for (int k = 0; k < 4; ++k)
+    if (th[k] != LBM_THERMAL_DIRICHLET && th[k] != LBM_THERMAL_ADIABATIC) return LBM_EINVAL;
+  if (p->psi_policy != 0 && p->psi_policy != 1) return LBM_EINVAL;
+  if (p->wall_x != 0 && p->wall_x != 1) return LBM_EINVAL;
+  if (p->wall_y != 0 && p->wall_y != 1) return LBM_EINVAL;
+  return LBM_OK;
+}
+
+Model make_model(const lbm_params *p, const Layout &L) {
+  Model m;
+  memset(&m, 0, sizeof(m));
+  m.nx = p->nx;
+  m.ny = p->ny;
+  m.pitch = L.pitch;
+  m.plane = L.plane;
+  m.inv_tau_f = 1.0 / p->tau_f;
+  m.inv_tau_g = 1.0 / p->tau_g;
+  m.kf = 1.0 - 1.0 / (2.0 * p->tau_f);
+  m.kg = 1.0 - 1.0 / (2.0 * p->tau_g);
+  m.G = p->G;
+  m.beta = p->beta;
+  m.sc_on = p->G != 0.0;
+  m.two_over_G = m.sc_on ? 2.0 / p->G : 0.0;
+  m.beta_one = p->beta == 1.0;
+  m.count_clamps = p->beta != 0.0;
+  m.eos = p->eos;
+  m.eos_fixed_T = p->eos_fixed_T != 0;
+  m.a = p->a;
+  m.b = p->b;
+  m.R = p->R;
+  m.T_eos = p->T_eos;
+  m.cv = p->cv;
+  m.inv_cv = 1.0 / p->cv;
+  m.gx = p->gx;
+  m.gy = p->gy;
+  m.wall_x = p->wall_x;
+  m.wall_y = p->wall_y;
+  m.thermal[0] = p->thermal_left;
+  m.thermal[1] = p->thermal_right;
+  m.thermal[2] = p->thermal_bottom;
+  m.thermal[3] = p->thermal_top;
+  m.wall_E[0] = p->cv * p->T_left;
+  m.wall_E[1] = p->cv * p->T_right;
+  m.wall_E[2] = p->cv * p->T_bottom;
+  m.wall_E[3] = p->cv * p->T_top;
+  if (p->precision == LBM_FP32_DEV) m.rho_ref = p->rho_ref;
+  if (p->precision != LBM_FP64) m.cvT_ref = p->cv * p->T_ref;
+  return m;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Layout L;
+  Model m;
+  Tiling t;        // step tiling
+  Tiling tm;       // moments tiling (fixed: sizes the partials buffer)
+  int st;          // lbmdev::Storage
+  hipStream_t stream;
+  char *ws;
+  void *buf[2];
+  int cur;
+  double *staging, *snap, *partials, *out;
+  unsigned long long *counters;
+  long long steps;
+  int initialized;
+  int check_every;
+};
+
+#define HIPCHK(expr)                        \
+  do {                                      \
+    if ((expr) != hipSuccess) return LBM_EDEVICE; \
+  } while (0)
+
+static int run_moments(lbm_ctx *h, double *rho, double *ux, double *uy, double *T, int write_snap,
+                       int compare_snap) {
+  lbmdev::MomentsOut mo;
+  memset(&mo, 0, sizeof(mo));
+  mo.rho = rho;
+  mo.ux = ux;
+  mo.uy = uy;
+  mo.T = T;
+  mo.snap_rho = h->snap;
+  mo.snap_T = h->snap + (size_t)h->p.nx * h->p.ny;
+  mo.write_snap = write_snap;
+  mo.compare_snap = compare_snap;
+  mo.partials = h->partials;
+  HIPCHK(lbmdev::launch_moments(h->m, h->tm, h->st, h->buf[h->cur], mo, h->stream));
+  HIPCHK(lbmdev::launch_finalize(h->partials, h->tm.strips * h->tm.bands, h->out, h->stream));
+  return LBM_OK;
+}
+
+// read back reductions + clamp counter; synchronizes
+static int fetch_totals(lbm_ctx *h, double red[lbmdev::kPartials], unsigned long long *clamps) {
+  HIPCHK(hipMemcpyAsync(red, h->out, lbmdev::kPartials * sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipMemcpyAsync(clamps, h->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+static int status_of(const lbm_ctx *h, const double red[lbmdev::kPartials], unsigned long long clamps) {
+  if (red[4] > 0.0 || !isfinite(red[0]) || !isfinite(red[1])) return LBM_ENONFINITE;
+  if (h->p.psi_policy == 1 && clamps > 0) return LBM_EDOMAIN;
+  return LBM_OK;
+}
+
+static int check(lbm_ctx *h) {
+  int rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 0, 0);
+  if (rc) return rc;
+  double red[lbmdev::kPartials];
+  unsigned long long clamps = 0;
+  rc = fetch_totals(h, red, &clamps);
+  if (rc) return rc;
+  return status_of(h, red, clamps);
+}
+
+extern "C" {
+
+// the kernels address each half (f or g planes) of a distribution buffer
+// with 32-bit byte offsets
+static bool fits_32bit(const Layout &L) {
+  return (unsigned long long)L.plane * L.elem * 9ULL < (1ULL << 32);
+}
+
+int lbm_workspace_bytes(const lbm_params *p, size_t *bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return LBM_EINVAL;
+  Layout L;
+  compute_layout(p, &L);
+  if (!fits_32bit(L)) return LBM_EINVAL;
+  *bytes = L.total;
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+               lbm_handle *out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign) != 0) return LBM_EINVAL;
+  Layout L;
+  compute_layout(p, &L);
+  if (!fits_32bit(L)) return LBM_EINVAL;
+  if (bytes < L.total) return LBM_ENOMEM;
+  lbm_ctx *h = new (std::nothrow) lbm_ctx;
+  if (!h) return LBM_ENOMEM;
+  memset(h, 0, sizeof(*h));
+  h->p = *p;
+  h->L = L;
+  h->m = make_model(p, L);
+  h->st = storage_of(p);
+  h->t = default_tiling(p->nx, p->ny, p->precision);
+  h->tm = h->t;
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char *)dev_workspace;
+  h->buf[0] = h->ws + L.off_buf[0];
+  h->buf[1] = h->ws + L.off_buf[1];
+  h->staging = (double *)(h->ws + L.off_staging);
+  h->snap = (double *)(h->ws + L.off_snap);
+  h->partials = (double *)(h->ws + L.off_partials);
+  h->out = (double *)(h->ws + L.off_out);
+  h->counters = (unsigned long long *)(h->ws + L.off_counters);
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_init_fields(lbm_handle h, const double *rho, const double *ux, const double *uy,
+                    const double *T) {
+  if (!h || !rho || !T) return LBM_EINVAL;
+  const size_t n = (size_t)h->p.nx * h->p.ny;
+  for (size_t c = 0; c < n; ++c) {
+    if (!(rho[c] > 0.0) || !isfinite(rho[c]) || !isfinite(T[c])) return LBM_EINVAL;
+    if (ux && !isfinite(ux[c])) return LBM_EINVAL;
+    if (uy && !isfinite(uy[c])) return LBM_EINVAL;
+  }
+  double *d_rho = h->staging, *d_T = h->staging + n, *d_ux = h->staging + 2 * n,
+         *d_uy = h->staging + 3 * n;
+  HIPCHK(hipMemcpyAsync(d_rho, rho, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(d_T, T, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (ux) HIPCHK(hipMemcpyAsync(d_ux, ux, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (uy) HIPCHK(hipMemcpyAsync(d_uy, uy, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(lbmdev::launch_init(h->m, h->st, h->buf[0], d_rho, ux ? d_ux : nullptr,
+                             uy ? d_uy : nullptr, d_T, h->stream));
+  HIPCHK(hipMemsetAsync(h->counters, 0, 8 * sizeof(unsigned long long), h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->cur = 0;
+  h->steps = 0;
+  h->initialized = 1;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle h, int n, int treatment) {
+  if (!h || n < 1) return LBM_EINVAL;
+  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  for (int k = 0; k < n; ++k) {
+    HIPCHK(lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur],
+                               treatment, h->counters, h->stream));
+    h->cur ^= 1;
+    h->steps += 1;
+    if (h->check_every > 0 && h->steps % h->check_every == 0) {
+      int rc = check(h);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_set_check_interval(lbm_handle h, int k) {
+  if (!h || k < 0) return LBM_EINVAL;
+  h->check_every = k;
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_handle h) {
+  if (!h) return LBM_EINVAL;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (!h->initialized) return LBM_OK;
+  return check(h);
+}
+
+int lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T) {
+  if (!h) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  const size_t n = (size_t)h->p.nx * h->p.ny;
+  double *s = h->staging;
+  int rc = run_moments(h, rho ? s : nullptr, ux ? s + n : nullptr, uy ? s + 2 * n : nullptr,
+                       T ? s + 3 * n : nullptr, 0, 0);
+  if (rc) return rc;
+  if (rho) HIPCHK(hipMemcpyAsync(rho, s, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (ux) HIPCHK(hipMemcpyAsync(ux, s + n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (uy) HIPCHK(hipMemcpyAsync(uy, s + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (T) HIPCHK(hipMemcpyAsync(T, s + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  double red[lbmdev::kPartials];
+  unsigned long long clamps = 0;
+  rc = fetch_totals(h, red, &clamps);
+  if (rc) return rc;
+  return status_of(h, red, clamps);
+}
+
+int lbm_moments_device(lbm_handle h, double *d_rho, double *d_ux, double *d_uy, double *d_T) {
+  if (!h) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  return run_moments(h, d_rho, d_ux, d_uy, d_T, 0, 0);
+}
+
+int lbm_totals(lbm_handle h, double out[8]) {
+  if (!h || !out) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  int rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 0, 0);
+  if (rc) return rc;
+  double red[lbmdev::kPartials];
+  unsigned long long clamps = 0;
+  rc = fetch_totals(h, red, &clamps);
+  if (rc) return rc;
+  out[0] = red[0];
+  out[1] = red[1];
+  out[2] = red[2];
+  out[3] = red[3];
+  out[4] = red[4];
+  out[5] = (double)clamps;
+  out[6] = (double)h->steps;
+  out[7] = 0.0;
+  return LBM_OK;
+}
+
+int lbm_step_residual(lbm_handle h, int treatment, double *residual) {
+  if (!h || !residual) return LBM_EINVAL;
+  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  int rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 1, 0);
+  if (rc) return rc;
+  HIPCHK(lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
+                             h->counters, h->stream));
+  h->cur ^= 1;
+  h->steps += 1;
+  rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 0, 1);
+  if (rc) return rc;
+  double red[lbmdev::kPartials];
+  unsigned long long clamps = 0;
+  rc = fetch_totals(h, red, &clamps);
+  if (rc) return rc;
+  const double r1 = red[6] > 0.0 ? red[5] / red[6] : 0.0;
+  const double r2 = red[8] > 0.0 ? red[7] / red[8] : 0.0;
+  *residual = r1 > r2 ? r1 : r2;
+  return status_of(h, red, clamps);
+}
+
+int lbm_get_state(lbm_handle h, double *state) {
+  if (!h || !state) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  const size_t n = (size_t)h->p.nx * h->p.ny;
+  for (int q = 0; q < 18; ++q) {
+    HIPCHK(lbmdev::launch_plane_to_f64(h->m, h->st, h->buf[h->cur], q, h->staging, h->stream));
+    HIPCHK(hipMemcpyAsync(state + (size_t)q * n, h->staging, n * sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_handle h, const double *state) {
+  if (!h || !state) return LBM_EINVAL;
+  const size_t n = (size_t)h->p.nx * h->p.ny;
+  for (size_t c = 0; c < 18 * n; ++c)
+    if (!isfinite(state[c])) return LBM_EINVAL;
+  if (h->st == lbmdev::ST_F32_LOCAL) {
+    // per-node reference from the density of the given state
+    double *rho = (double *)malloc(n * sizeof(double));
+    if (!rho) return LBM_ENOMEM;
+    for (size_t c = 0; c < n; ++c) {
+      double a = state[c];
+      for (int q = 1; q < 9; ++q) a += state[(size_t)q * n + c];
+      rho[c] = a;
+    }
+    hipError_t e = hipMemcpyAsync(h->staging, rho, n * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = lbmdev::launch_plane_from_f64(h->m, h->st, h->buf[h->cur], -1, h->staging, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    free(rho);
+    if (e != hipSuccess) return LBM_EDEVICE;
+  }
+  for (int q = 0; q < 18; ++q) {
+    HIPCHK(hipMemcpyAsync(h->staging, state + (size_t)q * n, n * sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(lbmdev::launch_plane_from_f64(h->m, h->st, h->buf[h->cur], q, h->staging, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  h->initialized = 1;
+  return LBM_OK;
+}
+
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int nx, ny, precision, cur;
+  long long steps;
+  unsigned long long clamps;
+  unsigned long long bytes;
+};
+}  // namespace
+
+int lbm_save(lbm_handle h, const char *path) {
+  if (!h || !path) return LBM_EINVAL;
+  if (!h->initialized) return LBM_ESTATE;
+  const size_t bytes = h->L.dist_bytes;
+  char *buf = (char *)malloc(bytes);
+  if (!buf) return LBM_ENOMEM;
+  CkptHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  memcpy(hd.magic, "LBMCKPT1", 8);
+  hd.nx = h->p.nx;
+  hd.ny = h->p.ny;
+  hd.precision = h->p.precision;
+  hd.steps = h->steps;
+  hd.bytes = bytes;
+  hipError_t e = hipMemcpyAsync(buf, h->buf[h->cur], bytes, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&hd.clamps, h->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    free(buf);
+    return LBM_EDEVICE;
+  }
+  FILE *fp = fopen(path, "wb");
+  int ok = fp && fwrite(&hd, sizeof(hd), 1, fp) == 1 && fwrite(buf, 1, bytes, fp) == bytes;
+  if (fp && fclose(fp) != 0) ok = 0;
+  free(buf);
+  return ok ? LBM_OK : LBM_EINVAL;
+}
+
+int lbm_load(lbm_handle h, const char *path) {
+  if (!h || !path) return LBM_EINVAL;
+  FILE *fp = fopen(path, "rb");
+  if (!fp) return LBM_EINVAL;
+  CkptHeader hd;
+  const size_t bytes = h->L.dist_bytes;
+  if (fread(&hd, sizeof(hd), 1, fp) != 1 || memcmp(hd.magic, "LBMCKPT1", 8) != 0 ||
+      hd.nx != h->p.nx || hd.ny != h->p.ny || hd.precision != h->p.precision || hd.bytes != bytes) {
+    fclose(fp);
+    return LBM_EINVAL;
+  }
+  char *buf = (char *)malloc(bytes);
+  if (!buf) {
+    fclose(fp);
+    return LBM_ENOMEM;
+  }
+  const int ok = fread(buf, 1, bytes, fp) == bytes;
+  fclose(fp);
+  if (!ok) {
+    free(buf);
+    return LBM_EINVAL;
+  }
+  hipError_t e = hipMemcpyAsync(h->buf[0], buf, bytes, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->counters, &hd.clamps, sizeof(unsigned long long), hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  free(buf);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  h->cur = 0;
+  h->steps = hd.steps;
+  h->initialized = 1;
+  return LBM_OK;
+}
+
+int lbm_set_tiling(lbm_handle h, int bx, int rows) {
+  if (!h) return LBM_EINVAL;
+  if (bx != 64 && bx != 128 && bx != 256) return LBM_EINVAL;
+  if (rows < 1) return LBM_EINVAL;
+  if (rows > h->p.ny) rows = h->p.ny;
+  h->t.bx = bx;
+  h->t.strips = (h->p.nx + bx - 3) / (bx - 2);
+  h->t.rows = rows;
+  h->t.bands = (h->p.ny + rows - 1) / rows;
+  return LBM_OK;
+}
+
+int lbm_get_tiling(lbm_handle h, int *bx, int *rows) {
+  if (!h || !bx || !rows) return LBM_EINVAL;
+  *bx = h->t.bx;
+  *rows = h->t.rows;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle h) {
+  if (!h) return LBM_EINVAL;
+  delete h;
+  return LBM_OK;
+}
+
+const char *lbm_strerror(int status) {
+  switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_ENONFINITE: return "non-finite density or energy";
+    case LBM_EDOMAIN: return "pseudopotential outside its real domain";
+    case LBM_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {
+  if (!dst || !src || bytes == 0 || bytes % 16 != 0) return LBM_EINVAL;
+  HIPCHK(lbmdev::launch_copy(dst, src, bytes, (hipStream_t)hip_stream));
+  return LBM_OK;
+}
+
+}  // extern "C"

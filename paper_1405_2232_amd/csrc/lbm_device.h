@@ -1,0 +1,101 @@
+// Internal device-side interface of liblbm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmdev {
+
+// How the 18 distributions of a node are stored.
+enum Storage {
+  ST_F64 = 0,        // FP64 values
+  ST_F32_GLOBAL = 1, // FP32 deviations from w_i rho_ref (g: w_i rho_ref cv T_ref)
+  ST_F32_LOCAL = 2   // FP32 deviations from w_i rho_bar, rho_bar a per-node FP16
+                     // density reference stored after the 18 planes
+};
+
+// Per-lattice constants of the model (Section II), pre-derived on the host.
+struct Model {
+  int nx, ny;
+  int pitch;                 // elements between rows of one plane
+  long long plane;           // elements between planes
+  double inv_tau_f, inv_tau_g;
+  double kf, kg;             // 1 - 1/(2 tau_f), 1 - 1/(2 tau_g)
+  double G, beta;
+  double two_over_G;         // 2/(G c^2) with c = 1
+  int sc_on;                 // G != 0
+  int beta_one;              // beta == 1: Eq. (2) only
+  int count_clamps;          // beta != 0 (a real psi is needed)
+  int eos;                   // 0 Carnahan-Starling, 1 ideal
+  int eos_fixed_T;
+  double a, b, R, T_eos;
+  double cv, inv_cv;
+  double gx, gy;
+  int wall_x, wall_y;
+  int thermal[4];            // left, right, bottom, top: 0 Dirichlet, 1 adiabatic
+  double wall_E[4];          // cv * T_w per wall (multiplied by the node's rho)
+  double rho_ref;            // ST_F32_GLOBAL density shift
+  double cvT_ref;            // cv * T_ref: energy shift per unit reference density
+};
+
+// What one launch of the tile kernel does.
+enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1 };
+
+// Output/side buffers of a moments launch (all optional).
+struct MomentsOut {
+  double *rho, *ux, *uy, *T;     // dense [ny][nx]
+  double *snap_rho, *snap_T;     // residual snapshot (dense)
+  int write_snap;                // 1: store rho, T into snap_*
+  int compare_snap;              // 1: accumulate max |phi - snap| and max |phi|
+  double *partials;              // per-block partial sums [block][kPartials]
+};
+
+constexpr int kPartials = 10;    // mass, energy, px, py, nonfinite, |drho|max, |rho|max, |dT|max, |T|max, 0
+
+// Tile geometry for one lattice.  A block of bx lanes covers bx consecutive
+// columns starting one column left of its strip; the bx - 2 inner lanes own
+// the strip, the two outer lanes only supply the psi halo.
+struct Tiling {
+  int bx;       // lanes per block
+  int rows;     // rows per band
+  int strips, bands;
+  int xcd;      // 1: place consecutive bands on the same XCD
+  int alt;      // 1: odd bands walk downwards
+  int nt;       // 1: non-temporal stores
+  int pf;       // rows of load look-ahead (1 or 2)
+};
+
+inline int strip_width(int bx) { return bx - 2; }
+
+// Launchers (stream-ordered, no synchronization).  Return hipError_t.
+hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                       int treatment, unsigned long long *clamp_counter, hipStream_t s);
+hipError_t launch_moments(const Model &m, const Tiling &t, int st, const void *src,
+                          const MomentsOut &o, hipStream_t s);
+hipError_t launch_init(const Model &m, int st, void *dst, const double *rho, const double *ux,
+                       const double *uy, const double *T, hipStream_t s);
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s);
+hipError_t launch_plane_to_f64(const Model &m, int st, const void *src, int q, double *out,
+                               hipStream_t s);
+hipError_t launch_plane_from_f64(const Model &m, int st, void *dst, int q, const double *in,
+                                 hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Byte offset of the FP16 reference plane inside one distribution buffer.
+__host__ __device__ inline size_t ref_plane_offset(const Model &m, int st) {
+  return st == ST_F64 ? 0 : (size_t)18 * (size_t)m.plane * sizeof(float);
+}
+
+// Batched step: many lattices, one launch.  Device tables: models[L],
+// offs[L] (byte offsets of each lattice in the two buffers), tiles[nblocks].
+struct BatchTile {
+  int lattice, strip, band, rows;
+  int dir;    // +1 up, -1 down
+  int pad[3];
+};
+hipError_t launch_batch_step(const Model *d_models, const long long *d_offsets,
+                             const BatchTile *d_tiles, int ntiles, int bx, int pf, int st,
+                             const void *src, void *dst, int treatment,
+                             unsigned long long *clamp_counter, hipStream_t s);
+
+}  // namespace lbmdev

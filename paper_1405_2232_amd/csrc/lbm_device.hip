@@ -1,0 +1,772 @@
+// HIP kernels (gfx950) of the fused D2Q9 thermal pseudopotential LB step.
+//
+// One step is one launch.  A block of BX lanes covers BX consecutive
+// columns: the inner BX-2 lanes own a strip of columns, the two outer lanes
+// supply the psi halo.  The block walks a band of rows (a sliding window
+// along y; odd bands may walk downwards):
+//   - the 18 distributions of the next rows are loaded one coalesced plane
+//     at a time, PF rows ahead of use;
+//   - the moments of row k+1 give rho and T, psi (Section II.A) goes to a
+//     ring of four LDS rows;
+//   - row k then reads the 3x3 psi stencil from LDS for the force of
+//     Eq. (2)/(4), collides f (Eq. (1)) and g (Eq. (7) or Eq. (24)) and
+//     pushes the results to the other buffer (ping-pong), with periodic
+//     wrap or bounce-back at walls.
+// Each distribution is read once and written once per step; only the psi
+// halo (one row per band edge, one column per strip edge) is read twice.
+// psi at a node needs the moments of its neighbours at the same time level,
+// so an in-place (A-A) update would let one block read neighbour data that
+// another block is overwriting; two buffers remove that race at no extra
+// HBM traffic.
+#include "lbm_device.h"
+
+namespace lbmdev {
+
+// D2Q9 velocity set, Section II.A: rest, E, N, W, S, NE, NW, SW, SE.
+struct Q9 {
+  static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+};
+
+template <typename S>
+__device__ __host__ constexpr S wgt(int i) {
+  return i == 0 ? S(4) / S(9) : (i < 5 ? S(1) / S(9) : S(1) / S(36));
+}
+
+// storage type S and arithmetic type C of each storage form: the per-node
+// reference form keeps FP32 storage but collides in FP64 (FP64 and FP32
+// vector ops issue at the same rate here, and rounding every intermediate
+// to FP32 costs an order of magnitude in accuracy at the interfaces)
+template <int ST>
+struct Prec;
+template <>
+struct Prec<ST_F64> {
+  using S = double;
+  using C = double;
+};
+template <>
+struct Prec<ST_F32_GLOBAL> {
+  using S = float;
+  using C = float;
+};
+template <>
+struct Prec<ST_F32_LOCAL> {
+  using S = float;
+  using C = double;
+};
+
+__device__ inline double pressure(const Model &m, double rho, double T) {
+  if (m.eos == 1) return rho * m.R * T;
+  const double eta = 0.25 * m.b * rho;
+  const double num = 1.0 + eta + eta * eta - eta * eta * eta;
+  const double om = 1.0 - eta;
+  return rho * m.R * T * num / (om * om * om) - m.a * rho * rho;
+}
+
+// psi^2 = 2 (p_EOS - rho c_s^2)/(G c^2); psi clamps to 0 outside the domain.
+__device__ inline void node_psi(const Model &m, double rho, double E, double &psi, double &s,
+                                int &clamped) {
+  clamped = 0;
+  if (!m.sc_on) {
+    psi = 0.0;
+    s = 0.0;
+    return;
+  }
+  const double T = m.eos_fixed_T ? m.T_eos : E * m.inv_cv / rho;
+  s = (pressure(m, rho, T) - rho * (1.0 / 3.0)) * m.two_over_G;
+  if (s >= 0.0) {
+    psi = sqrt(s);
+  } else {
+    psi = 0.0;
+    clamped = m.count_clamps;
+  }
+}
+
+// The density reference of a node in ST_F32_LOCAL storage: rho rounded to
+// FP16 (every block that computes a node's rho gets the same bits).
+__device__ inline float ref_of(double rho) { return (float)(_Float16)(float)rho; }
+
+// --- buffer addressing: one 32-bit byte offset per lane, plane offsets in SGPRs
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+
+struct Bufs {
+  __amdgpu_buffer_rsrc_t f, g, ref;
+};
+
+template <typename S>
+__device__ inline Bufs make_bufs(const void *base, const Model &m) {
+  const unsigned long long pb = (unsigned long long)m.plane * sizeof(S);
+  Bufs b;
+  char *p = (char *)base;
+  b.f = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(unsigned)(9 * pb), kRsrcWord3);
+  b.g = __builtin_amdgcn_make_buffer_rsrc(p + 9 * pb, (short)0, (int)(unsigned)(9 * pb), kRsrcWord3);
+  b.ref = __builtin_amdgcn_make_buffer_rsrc(p + 18 * pb, (short)0, (int)(unsigned)(m.plane * 2),
+                                            kRsrcWord3);
+  return b;
+}
+
+__device__ inline float bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float *) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ inline double bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double *) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
+template <typename S>
+struct Row {
+  S v[18];
+  float rb;  // reference density the stored deviations are taken from
+};
+
+template <typename C>
+struct Mom {
+  double rho, E;
+  C jx, jy;  // first moment of f
+  C sf, sg;  // deviation sums (rho - ref, E - ref * cvT_ref)
+};
+
+template <int BX>
+struct TileLds {
+  double psi[4][BX];
+  double s[4][BX];
+  float rbn[4][BX];  // new per-node references (ST_F32_LOCAL)
+  double red[BX];
+};
+
+template <int ST, int BX, int MODE, int PF>
+__device__ void tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
+                     int strip, int y0, int y1, int dir, int nt, int treatment,
+                     unsigned long long *clamp_counter, const MomentsOut &mo, TileLds<BX> &L,
+                     int block_id) {
+  using S = typename Prec<ST>::S;
+  using C = typename Prec<ST>::C;
+  const Bufs sb = make_bufs<S>(src_v, m);
+  const Bufs db = make_bufs<S>(dst_v, m);
+  const unsigned pb = (unsigned)(m.plane * (long long)sizeof(S));
+
+  const int lane = threadIdx.x;
+  const int nx = m.nx, ny = m.ny, pitch = m.pitch;
+  const int x0 = strip * (BX - 2);
+  const int nint = min(BX - 2, nx - x0);
+  const bool active = lane <= nint + 1;
+  const bool inner = lane >= 1 && lane <= nint;
+  const int x = x0 - 1 + lane;  // own column (inner lanes)
+  int xc = x;                   // column this lane loads: wrapped or mirrored
+  if (xc < 0) xc = m.wall_x ? 0 : nx - 1;
+  else if (xc >= nx) xc = m.wall_x ? nx - 1 : xc - nx;
+  if (!active) xc = 0;          // idle lanes read a valid node and store nothing
+
+  // push targets of an inner lane; -1 marks a wall
+  const int xl = x > 0 ? x - 1 : (m.wall_x ? -1 : nx - 1);
+  const int xr = x < nx - 1 ? x + 1 : (m.wall_x ? -1 : 0);
+  const bool lane_wall = xl < 0 || xr < 0;
+
+  auto map_row = [&](int r) -> int {
+    if (r < 0) return m.wall_y ? 0 : r + ny;
+    if (r >= ny) return m.wall_y ? ny - 1 : r - ny;
+    return r;
+  };
+
+  const int n = y1 - y0;
+  auto row_of = [&](int k) -> int { return dir > 0 ? y0 + k : y1 - 1 - k; };
+
+  long long clamps = 0;
+
+  auto load_row = [&](int k, Row<S> &d) {
+    const unsigned cell = (unsigned)(map_row(row_of(k)) * pitch + xc);
+    const unsigned off = cell * (unsigned)sizeof(S);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d.v[q] = bld(sb.f, off, (unsigned)q * pb, (S *)nullptr);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d.v[9 + q] = bld(sb.g, off, (unsigned)q * pb, (S *)nullptr);
+    if (ST == ST_F32_LOCAL) {
+      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(sb.ref, (int)(cell * 2u), 0, 0);
+      d.rb = (float)__builtin_bit_cast(_Float16, h);
+    }
+  };
+
+  // moments and psi of the row held in d; LDS ring slot = row & 3
+  auto psi_row = [&](int k, const Row<S> &d, Mom<C> &mm, bool keep) {
+    const int slot = row_of(k) & 3;
+    double sf, sg;
+    if (ST == ST_F32_LOCAL) {
+      float a = d.v[0];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) a += d.v[q];
+      float b = d.v[9];
+#pragma unroll
+      for (int q = 10; q < 18; ++q) b += d.v[q];
+      sf = (double)a;
+      sg = (double)b;
+    } else {
+      double a = (double)d.v[0];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) a += (double)d.v[q];
+      double b = (double)d.v[9];
+#pragma unroll
+      for (int q = 10; q < 18; ++q) b += (double)d.v[q];
+      sf = a;
+      sg = b;
+    }
+    const C v1 = (C)d.v[1], v2 = (C)d.v[2], v3 = (C)d.v[3], v4 = (C)d.v[4], v5 = (C)d.v[5],
+            v6 = (C)d.v[6], v7 = (C)d.v[7], v8 = (C)d.v[8];
+    mm.jx = ((v1 - v3) + (v5 - v6)) + (v8 - v7);
+    mm.jy = ((v2 - v4) + (v5 + v6)) - (v7 + v8);
+    const double ref = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)d.rb);
+    mm.sf = (C)sf;
+    mm.sg = (C)sg;
+    mm.rho = ref + sf;
+    mm.E = ref * m.cvT_ref + sg;
+    double psi, s;
+    int cl;
+    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    L.psi[slot][lane] = psi;
+    L.s[slot][lane] = s;
+    if (ST == ST_F32_LOCAL) L.rbn[slot][lane] = ref_of(mm.rho);
+    if (keep && inner) clamps += cl;
+  };
+
+  double acc[kPartials];
+#pragma unroll
+  for (int k = 0; k < kPartials; ++k) acc[k] = 0.0;
+
+  auto collide_row = [&](int k, const Row<S> &d, const Mom<C> &mm) {
+    if (!inner) return;
+    const int r = row_of(k);
+    const int c = lane;
+    const double *pm = L.psi[(r - 1) & 3];
+    const double *p0 = L.psi[r & 3];
+    const double *pp = L.psi[(r + 1) & 3];
+    double Fx = 0.0, Fy = 0.0;
+    if (m.sc_on) {
+      // Eq. (2): w(1) = 1/3 on the axes, w(2) = 1/12 on the diagonals
+      const double sx = (p0[c + 1] - p0[c - 1]) * (1.0 / 3.0) +
+                        ((pp[c + 1] - pp[c - 1]) + (pm[c + 1] - pm[c - 1])) * (1.0 / 12.0);
+      const double sy = (pp[c] - pm[c]) * (1.0 / 3.0) +
+                        ((pp[c + 1] + pp[c - 1]) - (pm[c + 1] + pm[c - 1])) * (1.0 / 12.0);
+      const double gb = -m.G * m.beta * p0[c];
+      Fx = gb * sx;
+      Fy = gb * sy;
+      if (!m.beta_one) {  // second term of Eq. (4), from psi^2
+        const double *qm = L.s[(r - 1) & 3];
+        const double *q0 = L.s[r & 3];
+        const double *qp = L.s[(r + 1) & 3];
+        const double tx2 = (q0[c + 1] - q0[c - 1]) * (1.0 / 3.0) +
+                           ((qp[c + 1] - qp[c - 1]) + (qm[c + 1] - qm[c - 1])) * (1.0 / 12.0);
+        const double ty2 = (qp[c] - qm[c]) * (1.0 / 3.0) +
+                           ((qp[c + 1] + qp[c - 1]) - (qm[c + 1] + qm[c - 1])) * (1.0 / 12.0);
+        const double h = -m.G * 0.5 * (1.0 - m.beta);
+        Fx += h * tx2;
+        Fy += h * ty2;
+      }
+    }
+    Fx += mm.rho * m.gx;
+    Fy += mm.rho * m.gy;
+
+    if (MODE == MODE_MOMENTS) {
+      const double ux = ((double)mm.jx + 0.5 * Fx) / mm.rho;
+      const double uy = ((double)mm.jy + 0.5 * Fy) / mm.rho;
+      const double T = mm.E * m.inv_cv / mm.rho;
+      const long long o = (long long)r * nx + x;
+      if (mo.rho) mo.rho[o] = mm.rho;
+      if (mo.ux) mo.ux[o] = ux;
+      if (mo.uy) mo.uy[o] = uy;
+      if (mo.T) mo.T[o] = T;
+      acc[0] += mm.rho;
+      acc[1] += mm.E;
+      acc[2] += (double)mm.jx + 0.5 * Fx;
+      acc[3] += (double)mm.jy + 0.5 * Fy;
+      acc[4] += (isfinite(mm.rho) && isfinite(mm.E)) ? 0.0 : 1.0;
+      if (mo.compare_snap) {
+        acc[5] = fmax(acc[5], fabs(mm.rho - mo.snap_rho[o]));
+        acc[6] = fmax(acc[6], fabs(mm.rho));
+        acc[7] = fmax(acc[7], fabs(T - mo.snap_T[o]));
+        acc[8] = fmax(acc[8], fabs(T));
+      }
+      if (mo.write_snap) {
+        mo.snap_rho[o] = mm.rho;
+        mo.snap_T[o] = T;
+      }
+      return;
+    }
+
+    // collision, Eq. (1) with the forcing term and Eq. (7)/(24), in C, on
+    // deviations from the node's own reference
+    const C rs = (C)mm.rho;
+    const C ir = C(1) / rs;
+    const C fx = (C)Fx, fy = (C)Fy;
+    const C ux = (mm.jx + C(0.5) * fx) * ir;
+    const C uy = (mm.jy + C(0.5) * fy) * ir;
+    const C uu = ux * ux + uy * uy;
+    const C uF = ux * fx + uy * fy;
+    const C Es = (C)mm.E;
+    const C dr = mm.sf, dE = mm.sg;
+    const C itf = (C)m.inv_tau_f, itg = (C)m.inv_tau_g, kf = (C)m.kf;
+    const C kgc = treatment == 1 ? (C)m.kg * (C(3) * Es * ir) : C(0);
+    const float rb_old = ST == ST_F32_LOCAL ? d.rb : 0.0f;
+    const float *rn_m = L.rbn[(r - 1) & 3];
+    const float *rn_0 = L.rbn[r & 3];
+    const float *rn_p = L.rbn[(r + 1) & 3];
+    const C cvTr = (C)m.cvT_ref;
+
+    const int rD = r > 0 ? r - 1 : (m.wall_y ? -1 : ny - 1);
+    const int rU = r < ny - 1 ? r + 1 : (m.wall_y ? -1 : 0);
+    const bool fast = rD >= 0 && rU >= 0 && !lane_wall;
+    const unsigned own = (unsigned)(r * pitch + x);
+    if (ST == ST_F32_LOCAL)
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)rn_0[c]),
+                                            db.ref, (int)(own * 2u), 0, 0);
+
+    constexpr int kx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int ky[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int ko[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    // post-collision values of direction i, relative to the own reference
+    auto post = [&](int i, C &fs, C &gs) {
+      const int exi = kx[i], eyi = ky[i];
+      const C eu = C(exi) * ux + C(eyi) * uy;
+      const C eF = C(exi) * fx + C(eyi) * fy;
+      const C X = C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu;
+      const C wi = wgt<C>(i);
+      const C feq = wi * (dr + rs * X);
+      const C Fi = kf * wi * (C(3) * (eF - uF) + C(9) * eu * eF);
+      const C fin = (C)d.v[i], gin = (C)d.v[9 + i];
+      fs = fin - (fin - feq) * itf + Fi;
+      const C geq = wi * (dE + Es * X);
+      gs = gin - (gin - geq) * itg + wi * kgc * eF;
+    };
+    // shift to the reference of the node the value lands in (ST_F32_LOCAL)
+    auto to_dest_ref = [&](int i, C &fs, C &gs) {
+      if (ST == ST_F32_LOCAL) {
+        const float *rr = ky[i] > 0 ? rn_p : (ky[i] < 0 ? rn_m : rn_0);
+        const C sh = wgt<C>(i) * (C)(rb_old - rr[c + kx[i]]);
+        fs += sh;
+        gs += sh * cvTr;
+      }
+    };
+    if (fast) {
+      // interior row and lane: every direction streams to x + e_i
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C fs, gs;
+        post(i, fs, gs);
+        to_dest_ref(i, fs, gs);
+        const int col = kx[i] > 0 ? xr : (kx[i] < 0 ? xl : x);
+        const int row = ky[i] > 0 ? rU : (ky[i] < 0 ? rD : r);
+        const unsigned off = (unsigned)(row * pitch + col) * (unsigned)sizeof(S);
+        bst(db.f, off, (unsigned)i * pb, (S)fs);
+        bst(db.g, off, (unsigned)i * pb, (S)gs);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C fs, gs;
+        post(i, fs, gs);
+        const int exi = kx[i], eyi = ky[i];
+        const int col = exi > 0 ? xr : (exi < 0 ? xl : x);
+        const int row = eyi > 0 ? rU : (eyi < 0 ? rD : r);
+        if (col >= 0 && row >= 0) {
+          to_dest_ref(i, fs, gs);
+          const unsigned off = (unsigned)(row * pitch + col) * (unsigned)sizeof(S);
+          bst(db.f, off, (unsigned)i * pb, (S)fs);
+          bst(db.g, off, (unsigned)i * pb, (S)gs);
+        } else {
+          // halfway bounce-back into the same node; the y wall wins at corners
+          const C wi = wgt<C>(i);
+          const bool hy = row < 0;
+          const int o = ko[i];
+          const int th = hy ? (eyi < 0 ? m.thermal[2] : m.thermal[3])
+                            : (exi < 0 ? m.thermal[0] : m.thermal[1]);
+          const double wE = hy ? (eyi < 0 ? m.wall_E[2] : m.wall_E[3])
+                               : (exi < 0 ? m.wall_E[0] : m.wall_E[1]);
+          C sh = C(0);
+          if (ST == ST_F32_LOCAL) sh = wi * (C)(rb_old - rn_0[c]);
+          C gb = gs + sh * cvTr;
+          if (th == 0) {
+            // anti-bounce-back with the wall value rho cv T_w (Dirichlet)
+            const double refE = ST == ST_F64 ? 0.0
+                                : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
+                                                       : (double)rb_old * m.cvT_ref);
+            const double refEn = ST == ST_F64 ? 0.0
+                                 : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
+                                                        : (double)rn_0[c] * m.cvT_ref);
+            gb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
+          }
+          const unsigned off = own * (unsigned)sizeof(S);
+          bst(db.f, off, (unsigned)o * pb, (S)(fs + sh));
+          bst(db.g, off, (unsigned)o * pb, (S)gb);
+        }
+      }
+    }
+  };
+
+  if (PF >= 2 && MODE == MODE_STEP) {
+    // three row buffers in rotating roles, unrolled so that no loaded
+    // register is copied (a copy would wait for the load in flight)
+    Row<S> R0, R1, R2;
+    Mom<C> M0, M1, M2;
+    load_row(-1, R2);
+    load_row(0, R0);
+    load_row(1, R1);
+    psi_row(-1, R2, M2, false);
+    psi_row(0, R0, M0, true);
+    auto iter = [&](int k, const Row<S> &cur, const Mom<C> &mc, const Row<S> &nxt, Mom<C> &mn,
+                    Row<S> &pre) {
+      // unconditional look-ahead: past the band it re-reads the band's last
+      // (halo) row, which the previous iteration left in cache
+      load_row(min(k + 2, n), pre);
+      psi_row(k + 1, nxt, mn, k + 1 < n);
+      __syncthreads();
+      collide_row(k, cur, mc);
+    };
+    for (int k = 0; k < n; k += 3) {
+      iter(k, R0, M0, R1, M1, R2);
+      if (k + 1 < n) iter(k + 1, R1, M1, R2, M2, R0);
+      if (k + 2 < n) iter(k + 2, R2, M2, R0, M0, R1);
+    }
+  } else {
+    Row<S> R0, R1;
+    Mom<C> M0, M1;
+    load_row(-1, R1);
+    psi_row(-1, R1, M1, false);
+    load_row(0, R0);
+    psi_row(0, R0, M0, true);
+    auto iter = [&](int k, const Row<S> &cur, const Mom<C> &mc, Row<S> &nxt, Mom<C> &mn) {
+      load_row(k + 1, nxt);
+      psi_row(k + 1, nxt, mn, k + 1 < n);
+      __syncthreads();
+      collide_row(k, cur, mc);
+    };
+    for (int k = 0; k < n; k += 2) {
+      iter(k, R0, M0, R1, M1);
+      if (k + 1 < n) iter(k + 1, R1, M1, R0, M0);
+    }
+  }
+
+  if (clamps && clamp_counter) atomicAdd(clamp_counter, (unsigned long long)clamps);
+
+  if (MODE == MODE_MOMENTS && mo.partials) {
+    // fixed-order block reduction of the per-lane partials
+    for (int k = 0; k < kPartials; ++k) {
+      __syncthreads();
+      L.red[lane] = acc[k];
+      __syncthreads();
+      for (int w = BX / 2; w > 0; w >>= 1) {
+        if (lane < w) L.red[lane] = (k >= 5) ? fmax(L.red[lane], L.red[lane + w]) : L.red[lane] + L.red[lane + w];
+        __syncthreads();
+      }
+      if (lane == 0) mo.partials[(long long)block_id * kPartials + k] = L.red[0];
+    }
+  }
+}
+
+// block -> tile: with t.xcd the grid (a multiple of 8) is dealt so that the
+// blocks landing on one XCD (round-robin dispatch) get consecutive tiles,
+// i.e. neighbouring bands, whose halo rows then meet in that XCD's L2.
+__device__ inline int tile_of_block(const Tiling &t) {
+  const int b = blockIdx.x;
+  if (!t.xcd) return b;
+  const int per = (int)gridDim.x >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int ST, int BX, int MODE, int PF>
+__global__ __launch_bounds__(BX) void k_tile(Model m, Tiling t, const void *__restrict__ src,
+                                             void *__restrict__ dst, int treatment,
+                                             unsigned long long *clamp_counter, MomentsOut mo) {
+  __shared__ TileLds<BX> L;
+  const int tid = tile_of_block(t);
+  if (tid >= t.strips * t.bands) return;
+  const int strip = tid % t.strips;
+  const int band = tid / t.strips;
+  const int y0 = band * t.rows;
+  const int y1 = min(y0 + t.rows, m.ny);
+  const int dir = (t.alt && (band & 1)) ? -1 : 1;
+  tile<ST, BX, MODE, PF>(m, src, dst, strip, y0, y1, dir, t.nt, treatment, clamp_counter, mo, L,
+                         tid);
+}
+
+template <int ST, int BX, int PF>
+__global__ __launch_bounds__(BX) void k_batch(const Model *__restrict__ models,
+                                              const long long *__restrict__ offs,
+                                              const BatchTile *__restrict__ tiles,
+                                              const char *__restrict__ src, char *__restrict__ dst,
+                                              int treatment, int nt,
+                                              unsigned long long *clamp_counter) {
+  __shared__ TileLds<BX> L;
+  const BatchTile bt = tiles[blockIdx.x];
+  const Model m = models[bt.lattice];
+  const long long off = offs[bt.lattice];
+  const int y0 = bt.band * bt.rows;
+  const int y1 = min(y0 + bt.rows, m.ny);
+  MomentsOut mo{};
+  tile<ST, BX, MODE_STEP, PF>(m, src + off, dst + off, bt.strip, y0, y1, bt.dir, nt, treatment,
+                              clamp_counter, mo, L, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+
+template <int ST>
+__global__ void k_init(Model m, void *__restrict__ dst_v, const double *__restrict__ rho,
+                       const double *__restrict__ ux, const double *__restrict__ uy,
+                       const double *__restrict__ T) {
+  using S = typename Prec<ST>::S;
+  S *dst = (S *)dst_v;
+  _Float16 *ref = (_Float16 *)((char *)dst_v + ref_plane_offset(m, ST));
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  const double r = rho[c];
+  const double u = ux ? ux[c] : 0.0, v = uy ? uy[c] : 0.0;
+  const double cvT = m.cv * T[c];
+  const double uu = u * u + v * v;
+  const long long idx = (long long)y * m.pitch + x;
+  double rf = 0.0;
+  if (ST == ST_F32_GLOBAL) rf = m.rho_ref;
+  if (ST == ST_F32_LOCAL) {
+    rf = (double)ref_of(r);
+    ref[idx] = (_Float16)(float)rf;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double eu = Q9::ex[i] * u + Q9::ey[i] * v;
+    const double w = wgt<double>(i);
+    const double feq = r * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    dst[i * m.plane + idx] = (S)(feq - w * rf);
+    dst[(9 + i) * m.plane + idx] = (S)(cvT * feq - w * rf * m.cvT_ref);
+  }
+}
+
+template <int ST>
+__global__ void k_plane_to(Model m, const void *__restrict__ src_v, int q, double *__restrict__ out) {
+  using S = typename Prec<ST>::S;
+  const S *src = (const S *)src_v;
+  const _Float16 *ref = (const _Float16 *)((const char *)src_v + ref_plane_offset(m, ST));
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  const long long idx = (long long)y * m.pitch + x;
+  const int i = q < 9 ? q : q - 9;
+  double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  if (q >= 9) rf *= m.cvT_ref;
+  out[c] = (double)src[q * m.plane + idx] + wgt<double>(i) * rf;
+}
+
+template <int ST>
+__global__ void k_plane_from(Model m, void *__restrict__ dst_v, int q, const double *__restrict__ in) {
+  using S = typename Prec<ST>::S;
+  S *dst = (S *)dst_v;
+  const _Float16 *ref = (const _Float16 *)((const char *)dst_v + ref_plane_offset(m, ST));
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  const long long idx = (long long)y * m.pitch + x;
+  const int i = q < 9 ? q : q - 9;
+  double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  if (q >= 9) rf *= m.cvT_ref;
+  dst[q * m.plane + idx] = (S)(in[c] - wgt<double>(i) * rf);
+}
+
+// reference plane of ST_F32_LOCAL from a dense FP64 density field
+__global__ void k_ref_from_rho(Model m, void *__restrict__ dst_v, const double *__restrict__ rho) {
+  _Float16 *ref = (_Float16 *)((char *)dst_v + ref_plane_offset(m, ST_F32_LOCAL));
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  ref[(long long)y * m.pitch + x] = (_Float16)ref_of(rho[c]);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks,
+                                                  double *__restrict__ out) {
+  __shared__ double red[256];
+  const int tx = threadIdx.x;
+  for (int k = 0; k < kPartials; ++k) {
+    const bool is_max = k >= 5;
+    double a = 0.0;
+    for (int b = tx; b < nblocks; b += 256) {
+      const double v = partials[(long long)b * kPartials + k];
+      a = is_max ? fmax(a, v) : a + v;
+    }
+    red[tx] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tx < w) red[tx] = is_max ? fmax(red[tx], red[tx + w]) : red[tx] + red[tx + w];
+      __syncthreads();
+    }
+    if (tx == 0) out[k] = red[0];
+    __syncthreads();
+  }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// plain streaming copy: each lane moves four 16-byte words per trip
+__global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
+                                              long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x * 4;
+  for (long long i = ((long long)blockIdx.x * blockDim.x * 4) + threadIdx.x; i < n; i += stride) {
+    u32x4 a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + k * 256 < n) a[k] = src[i + k * 256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + k * 256 < n) __builtin_nontemporal_store(a[k], &dst[i + k * 256]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+static inline unsigned grid1d(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static inline unsigned tile_grid(const Tiling &t) {
+  unsigned g = (unsigned)(t.strips * t.bands);
+  if (t.xcd) g = (g + 7u) & ~7u;
+  return g;
+}
+
+template <int ST, int MODE, int PF>
+static hipError_t launch_tile_t(const Model &m, const Tiling &t, const void *src, void *dst,
+                                int treatment, unsigned long long *cc, const MomentsOut &mo,
+                                hipStream_t s) {
+  const unsigned grid = tile_grid(t);
+  switch (t.bx) {
+    case 64:
+      hipLaunchKernelGGL((k_tile<ST, 64, MODE, PF>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc, mo);
+      break;
+    case 128:
+      hipLaunchKernelGGL((k_tile<ST, 128, MODE, PF>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc, mo);
+      break;
+    case 256:
+      hipLaunchKernelGGL((k_tile<ST, 256, MODE, PF>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc, mo);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE, int PF>
+static hipError_t launch_tile_st(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                                 int treatment, unsigned long long *cc, const MomentsOut &mo,
+                                 hipStream_t s) {
+  switch (st) {
+    case ST_F64: return launch_tile_t<ST_F64, MODE, PF>(m, t, src, dst, treatment, cc, mo, s);
+    case ST_F32_GLOBAL: return launch_tile_t<ST_F32_GLOBAL, MODE, PF>(m, t, src, dst, treatment, cc, mo, s);
+    case ST_F32_LOCAL: return launch_tile_t<ST_F32_LOCAL, MODE, PF>(m, t, src, dst, treatment, cc, mo, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                       int treatment, unsigned long long *cc, hipStream_t s) {
+  MomentsOut mo{};
+  if (t.pf >= 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
+  return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+}
+
+hipError_t launch_moments(const Model &m, const Tiling &t, int st, const void *src,
+                          const MomentsOut &o, hipStream_t s) {
+  return launch_tile_st<MODE_MOMENTS, 1>(m, t, st, src, nullptr, 0, nullptr, o, s);
+}
+
+hipError_t launch_init(const Model &m, int st, void *dst, const double *rho, const double *ux,
+                       const double *uy, const double *T, hipStream_t s) {
+  const long long n = (long long)m.nx * m.ny;
+  const dim3 g(grid1d(n, 256)), b(256);
+  switch (st) {
+    case ST_F64: hipLaunchKernelGGL(k_init<ST_F64>, g, b, 0, s, m, dst, rho, ux, uy, T); break;
+    case ST_F32_GLOBAL: hipLaunchKernelGGL(k_init<ST_F32_GLOBAL>, g, b, 0, s, m, dst, rho, ux, uy, T); break;
+    case ST_F32_LOCAL: hipLaunchKernelGGL(k_init<ST_F32_LOCAL>, g, b, 0, s, m, dst, rho, ux, uy, T); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_to_f64(const Model &m, int st, const void *src, int q, double *out,
+                               hipStream_t s) {
+  const long long n = (long long)m.nx * m.ny;
+  const dim3 g(grid1d(n, 256)), b(256);
+  switch (st) {
+    case ST_F64: hipLaunchKernelGGL(k_plane_to<ST_F64>, g, b, 0, s, m, src, q, out); break;
+    case ST_F32_GLOBAL: hipLaunchKernelGGL(k_plane_to<ST_F32_GLOBAL>, g, b, 0, s, m, src, q, out); break;
+    case ST_F32_LOCAL: hipLaunchKernelGGL(k_plane_to<ST_F32_LOCAL>, g, b, 0, s, m, src, q, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_from_f64(const Model &m, int st, void *dst, int q, const double *in,
+                                 hipStream_t s) {
+  const long long n = (long long)m.nx * m.ny;
+  const dim3 g(grid1d(n, 256)), b(256);
+  switch (st) {
+    case ST_F64: hipLaunchKernelGGL(k_plane_from<ST_F64>, g, b, 0, s, m, dst, q, in); break;
+    case ST_F32_GLOBAL: hipLaunchKernelGGL(k_plane_from<ST_F32_GLOBAL>, g, b, 0, s, m, dst, q, in); break;
+    case ST_F32_LOCAL:
+      if (q < 0) hipLaunchKernelGGL(k_ref_from_rho, g, b, 0, s, m, dst, in);
+      else hipLaunchKernelGGL(k_plane_from<ST_F32_LOCAL>, g, b, 0, s, m, dst, q, in);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 16);
+  long long blocks = (n + 1023) / 1024;
+  if (blocks > 256 * 32) blocks = 256 * 32;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4 *)dst, (const u32x4 *)src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const Model *d_models, const long long *d_offsets,
+                             const BatchTile *d_tiles, int ntiles, int bx, int pf, int st,
+                             const void *src, void *dst, int treatment,
+                             unsigned long long *cc, hipStream_t s) {
+  const dim3 g((unsigned)ntiles);
+  const char *sp = (const char *)src;
+  char *dp = (char *)dst;
+  const int nt = 0;
+#define LBM_B(ST_, B_, PF_)                                                                      \
+  hipLaunchKernelGGL((k_batch<ST_, B_, PF_>), g, dim3(B_), 0, s, d_models, d_offsets, d_tiles, sp, \
+                     dp, treatment, nt, cc)
+#define LBM_BX(ST_, PF_)                      \
+  do {                                        \
+    if (bx == 64) LBM_B(ST_, 64, PF_);        \
+    else if (bx == 128) LBM_B(ST_, 128, PF_); \
+    else if (bx == 256) LBM_B(ST_, 256, PF_); \
+    else return hipErrorInvalidValue;         \
+  } while (0)
+  if (st == ST_F64) {
+    LBM_BX(ST_F64, 1);
+  } else if (st == ST_F32_GLOBAL) {
+    if (pf >= 2) LBM_BX(ST_F32_GLOBAL, 2); else LBM_BX(ST_F32_GLOBAL, 1);
+  } else if (st == ST_F32_LOCAL) {
+    if (pf >= 2) LBM_BX(ST_F32_LOCAL, 2); else LBM_BX(ST_F32_LOCAL, 1);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef LBM_BX
+#undef LBM_B
+  return hipGetLastError();
+}
+
+}  // namespace lbmdev

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/lbm.h declares, and its parameter validation works without a GPU
+(no compute call is made here)."""
+import ctypes
+
+import pytest
+
+from paper_1405_2232_amd import inputs, lbm
+
+
+def test_library_exports_every_declared_symbol():
+    names = lbm.header_functions()
+    assert len(names) >= 17
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_header_and_binding_struct_agree():
+    """The ctypes mirror has one field per lbm_params member, in order."""
+    import re
+    txt = re.sub(r"/\*.*?\*/", "", open(lbm.HEADER).read(), flags=re.S)
+    body = txt[txt.index("typedef struct {") + len("typedef struct {"):txt.index("} lbm_params;")]
+    decl = []
+    for stmt in body.split(";"):
+        stmt = stmt.strip()
+        if not stmt:
+            continue
+        typ, rest = stmt.split(None, 1)
+        decl += [(typ, n.strip()) for n in rest.split(",")]
+    fields = lbm.Params._fields_
+    assert [n for n, _ in fields] == [n for _, n in decl]
+    for (name, ct), (typ, _) in zip(fields, decl):
+        assert (ct is ctypes.c_int) == (typ == "int"), name
+        assert (ct is ctypes.c_double) == (typ == "double"), name
+
+
+def _bytes(cfg, **kw):
+    p = lbm.make_params(cfg, **kw)
+    n = ctypes.c_size_t()
+    rc = lbm.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_bytes_scale_with_precision():
+    p, _, _ = inputs.static_droplet()
+    rc64, b64 = _bytes(p, precision="fp64")
+    rc32, b32 = _bytes(p, precision="fp32dev", rho_ref=0.1, T_ref=0.08)
+    assert rc64 == 0 and rc32 == 0
+    # two buffers of 18 planes dominate: 2*18*64*64*8 bytes for FP64
+    assert b64 >= 2 * 18 * 64 * 64 * 8
+    assert b32 >= 2 * 18 * 64 * 64 * 4
+    assert b32 < b64
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau_f=0.5), dict(tau_g=0.4), dict(nx=0), dict(ny=-3), dict(cv=0.0),
+    dict(eos="cs", psi_policy=3), dict(tau_f=float("nan")),
+])
+def test_parameter_validation(bad):
+    p, _, _ = inputs.static_droplet()
+    p.update(bad)
+    rc, _ = _bytes(p)
+    assert rc == lbm.EINVAL
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    p, _, _ = inputs.static_droplet()
+    rc, need = _bytes(p)
+    assert rc == 0
+    P = lbm.make_params(p)
+    h = ctypes.c_void_p()
+    L = lbm.lib()
+    # nothing is dereferenced: creation only carves the workspace
+    fake = ctypes.c_void_p(1 << 40)
+    assert L.lbm_create(ctypes.byref(P), fake, need - 256, None, ctypes.byref(h)) == lbm.ENOMEM
+    assert L.lbm_create(ctypes.byref(P), ctypes.c_void_p((1 << 40) + 8), need, None,
+                        ctypes.byref(h)) == lbm.EINVAL
+    assert L.lbm_create(ctypes.byref(P), fake, need, None, ctypes.byref(h)) == lbm.OK
+    # out-of-order and bad-argument calls fail before touching the device
+    assert L.lbm_step(h, 1, lbm.PLAIN) == lbm.ESTATE
+    assert L.lbm_step(h, 0, lbm.PLAIN) == lbm.EINVAL
+    assert L.lbm_step(h, 1, 7) == lbm.EINVAL
+    assert L.lbm_set_tiling(h, 96, 4) == lbm.EINVAL
+    assert L.lbm_set_tiling(h, 128, 0) == lbm.EINVAL
+    assert L.lbm_set_tiling(h, 128, 5) == lbm.OK
+    bx, rows = ctypes.c_int(), ctypes.c_int()
+    assert L.lbm_get_tiling(h, ctypes.byref(bx), ctypes.byref(rows)) == lbm.OK
+    assert (bx.value, rows.value) == (128, 5)
+    assert L.lbm_destroy(h) == lbm.OK
+
+
+def test_strerror_names_every_status():
+    L = lbm.lib()
+    seen = set()
+    for s in (lbm.OK, lbm.EINVAL, lbm.ENOMEM, lbm.EDEVICE, lbm.ENONFINITE, lbm.EDOMAIN, lbm.ESTATE):
+        msg = L.lbm_strerror(s).decode()
+        assert msg and msg != "unknown status"
+        seen.add(msg)
+    assert len(seen) == 7
