@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9 thermal pseudopotential LB step on one GPU.
+
+Workload: the 2048 x 2048 flat two-phase slab (liquid in the middle half,
+Carnahan-Starling EOS at 0.85 T_c, walls at 0.80 T_c and 0.90 T_c, periodic
+in x), corrected temperature treatment (Eq. (24)), EOS at the local
+temperature, distributions stored in FP32 with a per-node density reference
+(the storage form that meets the FP64 oracle's tolerances).  One step = one
+fused launch (moments, psi, force, collision of f and g, streaming with
+bounce-back walls); the FP64 reduction check runs every 100 steps and the
+FP64 moments are exported once at the end of the timed region.
+
+Prints one JSON line.  `value` is MLUPS (lattice updates per second / 1e6)
+with the state resident in HBM.  `roofline` prices the step kernel's
+algorithmic bytes (18 distributions read + written per node, 144 B in FP32)
+against the 8 TB/s HBM peak; `cpu_baseline` times the FP64 oracle on the
+host cores over a bounded number of steps of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES = {"fp32local": 144, "fp32dev": 144, "fp64": 288}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic_wall_slab_2048.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1405_2232_amd", "csrc", f)
+                  for f in ("lbm_device.hip", "lbm_device.h")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--nx", type=int, default=2048)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--precision", default="fp32local", choices=sorted(ALG_BYTES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP64/FP32-global side runs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe_only(nbytes):
+    """Ten launches of the plain streaming copy over `nbytes`: the reference
+    for scaling byte counters and the practical bandwidth ceiling."""
+    import torch
+    from paper_1405_2232_amd.lbm import copy_probe
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    copy_probe(b, a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        copy_probe(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_bytes": nbytes, "ms": round(ms, 5),
+                      "GBs": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+
+
+def timed_steps(g, steps, treatment, torch):
+    """Average duration of one step launch, from HIP events on the stream
+    the library launches on (torch's current stream)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    g.step(steps, treatment)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(p, rho, T, treatment, seconds):
+    """FP64 oracle on the host cores: time whole steps of the same workload
+    until about `seconds` have passed."""
+    from oracle import Oracle
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    o.step(1, treatment)  # first touch
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1, treatment)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    cells = p["nx"] * p["ny"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d steps of the %dx%d slab (FP64 oracle, %d OpenMP threads, %.1f s)"
+                      % (n, p["nx"], p["ny"], cores, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the slab would shard as y-slabs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe_only(args.copy_probe)
+        return
+    import torch
+    from paper_1405_2232_amd import inputs
+    from paper_1405_2232_amd.lbm import CORRECTED, Lattice
+
+    torch.cuda.set_device(0)
+    p, rho, T = inputs.wall_slab(nx=args.nx, ny=args.ny)
+    cells = args.nx * args.ny
+    treatment = CORRECTED
+
+    g = Lattice(p, args.precision)
+    g.init_fields(rho, T)
+    g.set_check_interval(100)
+    if args.warmup > 0:
+        g.step(args.warmup, treatment)
+    out = [torch.empty((args.ny, args.nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+    torch.cuda.synchronize()
+
+    # timed region: K steps (with the periodic FP64 check) + one moments export
+    t0 = time.perf_counter()
+    g.step(args.steps, treatment)
+    g.moments_device(*out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = g.sync()
+    if status != 0:
+        raise SystemExit("the run reported status %d" % status)
+    ms_per_step = wall * 1e3 / args.steps
+    mlups = cells * args.steps / wall / 1e6
+
+    # step kernel alone, HIP events on the launch stream
+    g.set_check_interval(0)
+    k_steps = min(500, max(50, args.steps // 4))
+    kernel_ms = timed_steps(g, k_steps, treatment, torch)
+    achieved = ALG_BYTES[args.precision] * cells / (kernel_ms * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fp:
+            tr = json.load(fp)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("precision") == args.precision \
+                and tr.get("nx") == args.nx and tr.get("ny") == args.ny:
+            traffic = tr.get("bytes_per_launch")
+
+    extra = {}
+    if not args.no_extra:
+        for prec in ("fp64", "fp32dev"):
+            if prec == args.precision:
+                continue
+            h = Lattice(p, prec)
+            h.init_fields(rho, T)
+            h.step(50, treatment)
+            ms = timed_steps(h, 200, treatment, torch)
+            extra[prec] = {"mlups": round(cells / ms / 1e3, 1),
+                           "alg_GBs": round(ALG_BYTES[prec] * cells / ms / 1e6, 1)}
+            del h
+        extra[args.precision] = {"mlups": round(cells / kernel_ms / 1e3, 1),
+                                 "alg_GBs": round(achieved, 1)}
+
+    line = {
+        "metric": "MLUPS (FP64 vs FP32-dev, % HBM roofline); wall-time to 1e-8 residual vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": {"fp32local": "f32 + f16 node reference", "fp32dev": "f32",
+                    "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "wall_slab_%dx%d_corrected_%s" % (args.nx, args.ny, args.precision),
+                   "nx": args.nx, "ny": args.ny, "treatment": "corrected (Eq. 24)",
+                   "eos": "Carnahan-Starling at local T", "T0": "0.85 Tc",
+                   "walls": "0.80 Tc / 0.90 Tc", "check_every": 100},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
+                     "bytes_per_node": ALG_BYTES[args.precision]},
+        "by_precision": extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, rho, T, treatment, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
