@@ -36,25 +36,21 @@ struct Layout {
 
 long long env_ll(const char *name, long long dflt);
 
-// Default tile shape: wide strips (inner width bx - 2), bands tall enough
-// that the two halo rows per band stay a small fraction of the loads, and
-// enough blocks to keep every compute unit busy.
+// Default tile shape: wide strips (inner width bx - 2) and bands of 8 rows.
+// Short bands give many blocks (the step is latency-bound at two waves per
+// SIMD) and their two halo rows are re-read from L2 by the neighbouring band
+// running on the same XCD at the same time.
 Tiling default_tiling(int nx, int ny, int precision) {
   Tiling t;
   t.bx = nx >= 192 ? 256 : (nx > 62 ? 128 : 64);
   t.strips = (nx + t.bx - 3) / (t.bx - 2);
-  const int target = 1024;
-  int bands = target / t.strips;
-  if (bands < 1) bands = 1;
-  int rows = (ny + bands - 1) / bands;
-  if (rows < 16) rows = 16;
-  if (rows > ny) rows = ny;
-  t.rows = rows;
-  t.bands = (ny + rows - 1) / rows;
+  t.rows = ny < 8 ? ny : 8;
+  t.bands = (ny + t.rows - 1) / t.rows;
   t.xcd = 1;
   t.alt = 1;
   t.nt = 0;
-  t.pf = precision == LBM_FP64 ? 1 : 2;
+  t.pf = 2;
+  (void)precision;
   // experiment knobs (environment) override the defaults
   const long long ebx = env_ll("LBM_BX", 0), erows = env_ll("LBM_ROWS", 0);
   if (ebx == 64 || ebx == 128 || ebx == 256) t.bx = (int)ebx;
@@ -84,9 +80,12 @@ bool compute_layout(const lbm_params *p, Layout *L) {
   L->elem = fp32 ? 4 : 8;
   const int align_elems = (int)(kAlign / L->elem);
   L->pitch = (int)align_up((size_t)p->nx, (size_t)align_elems);
-  const long long pad = env_ll("LBM_PLANE_PAD", 0);
-  L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) +
-             (pad > 0 ? pad * align_elems : 0);
+  // each plane ends in a 4 KiB pad: it staggers the 18 streams of a row
+  // over HBM channels and holds the slots that lanes owning no node store
+  // into (the kernels need at least 256 elements there)
+  long long pad = env_ll("LBM_PLANE_PAD", 16) * align_elems;
+  if (pad < 256) pad = 256;
+  L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) + pad;
   // 18 planes, then (LBM_FP32_LOCAL) one FP16 reference plane
   L->dist_bytes = align_up((size_t)L->plane * 18 * L->elem +
                                (p->precision == LBM_FP32_LOCAL ? (size_t)L->plane * 2 : 0),

@@ -133,7 +133,7 @@ struct Mom {
   C sf, sg;  // deviation sums (rho - ref, E - ref * cvT_ref)
 };
 
-template <int BX>
+template <int BX, typename S>
 struct TileLds {
   double psi[4][BX];
   double s[4][BX];
@@ -144,7 +144,7 @@ struct TileLds {
 template <int ST, int BX, int MODE, int PF>
 __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
                      int strip, int y0, int y1, int dir, int nt, int treatment,
-                     unsigned long long *clamp_counter, const MomentsOut &mo, TileLds<BX> &L,
+                     unsigned long long *clamp_counter, const MomentsOut &mo, TileLds<BX, typename Prec<ST>::S> &L,
                      int block_id) {
   using S = typename Prec<ST>::S;
   using C = typename Prec<ST>::C;
@@ -167,7 +167,6 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
   // push targets of an inner lane; -1 marks a wall
   const int xl = x > 0 ? x - 1 : (m.wall_x ? -1 : nx - 1);
   const int xr = x < nx - 1 ? x + 1 : (m.wall_x ? -1 : 0);
-  const bool lane_wall = xl < 0 || xr < 0;
 
   auto map_row = [&](int r) -> int {
     if (r < 0) return m.wall_y ? 0 : r + ny;
@@ -239,9 +238,9 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
   for (int k = 0; k < kPartials; ++k) acc[k] = 0.0;
 
   auto collide_row = [&](int k, const Row<S> &d, const Mom<C> &mm) {
-    if (!inner) return;
+    if (MODE == MODE_MOMENTS && !inner) return;
     const int r = row_of(k);
-    const int c = lane;
+    const int c = inner ? lane : 1;  // outer lanes compute on a valid stencil, store nothing
     const double *pm = L.psi[(r - 1) & 3];
     const double *p0 = L.psi[r & 3];
     const double *pp = L.psi[(r + 1) & 3];
@@ -319,11 +318,12 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
 
     const int rD = r > 0 ? r - 1 : (m.wall_y ? -1 : ny - 1);
     const int rU = r < ny - 1 ? r + 1 : (m.wall_y ? -1 : 0);
-    const bool fast = rD >= 0 && rU >= 0 && !lane_wall;
+    const bool row_wall = rD < 0 || rU < 0;  // uniform over the block
     const unsigned own = (unsigned)(r * pitch + x);
     if (ST == ST_F32_LOCAL)
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)rn_0[c]),
-                                            db.ref, (int)(own * 2u), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b16(
+          __builtin_bit_cast(unsigned short, (_Float16)rn_0[c]), db.ref,
+          (int)((inner ? own : (unsigned)(ny * pitch + lane)) * 2u), 0, 0);
 
     constexpr int kx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ky[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -351,8 +351,13 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         gs += sh * cvTr;
       }
     };
-    if (fast) {
-      // interior row and lane: every direction streams to x + e_i
+    // Every lane issues the same 18 stores whatever its case, so the next
+    // row's loads never wait for a store that sat in a masked branch; a lane
+    // that owns no node writes into the unused pad past the end of the
+    // plane, at a slot of its own.
+    const unsigned dummy = (unsigned)(ny * pitch + lane);
+    const unsigned sz = (unsigned)sizeof(S);
+    if (!(row_wall || m.wall_x)) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         C fs, gs;
@@ -360,9 +365,9 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         to_dest_ref(i, fs, gs);
         const int col = kx[i] > 0 ? xr : (kx[i] < 0 ? xl : x);
         const int row = ky[i] > 0 ? rU : (ky[i] < 0 ? rD : r);
-        const unsigned off = (unsigned)(row * pitch + col) * (unsigned)sizeof(S);
-        bst(db.f, off, (unsigned)i * pb, (S)fs);
-        bst(db.g, off, (unsigned)i * pb, (S)gs);
+        const unsigned cell = inner ? (unsigned)(row * pitch + col) : dummy;
+        bst(db.f, cell * sz + (unsigned)i * pb, 0u, (S)fs);
+        bst(db.g, cell * sz + (unsigned)i * pb, 0u, (S)gs);
       }
     } else {
 #pragma unroll
@@ -372,37 +377,35 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         const int exi = kx[i], eyi = ky[i];
         const int col = exi > 0 ? xr : (exi < 0 ? xl : x);
         const int row = eyi > 0 ? rU : (eyi < 0 ? rD : r);
-        if (col >= 0 && row >= 0) {
-          to_dest_ref(i, fs, gs);
-          const unsigned off = (unsigned)(row * pitch + col) * (unsigned)sizeof(S);
-          bst(db.f, off, (unsigned)i * pb, (S)fs);
-          bst(db.g, off, (unsigned)i * pb, (S)gs);
-        } else {
-          // halfway bounce-back into the same node; the y wall wins at corners
-          const C wi = wgt<C>(i);
-          const bool hy = row < 0;
-          const int o = ko[i];
-          const int th = hy ? (eyi < 0 ? m.thermal[2] : m.thermal[3])
-                            : (exi < 0 ? m.thermal[0] : m.thermal[1]);
-          const double wE = hy ? (eyi < 0 ? m.wall_E[2] : m.wall_E[3])
-                               : (exi < 0 ? m.wall_E[0] : m.wall_E[1]);
-          C sh = C(0);
-          if (ST == ST_F32_LOCAL) sh = wi * (C)(rb_old - rn_0[c]);
-          C gb = gs + sh * cvTr;
-          if (th == 0) {
-            // anti-bounce-back with the wall value rho cv T_w (Dirichlet)
-            const double refE = ST == ST_F64 ? 0.0
-                                : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
-                                                       : (double)rb_old * m.cvT_ref);
-            const double refEn = ST == ST_F64 ? 0.0
-                                 : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
-                                                        : (double)rn_0[c] * m.cvT_ref);
-            gb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
-          }
-          const unsigned off = own * (unsigned)sizeof(S);
-          bst(db.f, off, (unsigned)o * pb, (S)(fs + sh));
-          bst(db.g, off, (unsigned)o * pb, (S)gb);
+        const bool stays = col >= 0 && row >= 0;
+        const C wi = wgt<C>(i);
+        // reference of the node the value lands in (ST_F32_LOCAL)
+        C sh = C(0);
+        if (ST == ST_F32_LOCAL) {
+          const float *rr = eyi > 0 ? rn_p : (eyi < 0 ? rn_m : rn_0);
+          const float rd = stays ? rr[c + exi] : rn_0[c];
+          sh = wi * (C)(rb_old - rd);
         }
+        // halfway bounce-back into the same node; the y wall wins at corners;
+        // Dirichlet walls anti-bounce-back with the wall value rho cv T_w
+        const bool hy = row < 0;
+        const int th = hy ? (eyi < 0 ? m.thermal[2] : m.thermal[3])
+                          : (exi < 0 ? m.thermal[0] : m.thermal[1]);
+        const double wE = hy ? (eyi < 0 ? m.wall_E[2] : m.wall_E[3])
+                             : (exi < 0 ? m.wall_E[0] : m.wall_E[1]);
+        const double refE = ST == ST_F64 ? 0.0
+                            : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
+                                                   : (double)rb_old * m.cvT_ref);
+        const double refEn = ST == ST_F64 ? 0.0
+                             : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
+                                                    : (double)rn_0[c] * m.cvT_ref);
+        const C g_abb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
+        const C g_out = (stays || th != 0) ? gs + sh * cvTr : g_abb;
+        const C f_out = fs + sh;
+        const unsigned q = stays ? (unsigned)i : (unsigned)ko[i];
+        const unsigned cell = !inner ? dummy : (stays ? (unsigned)(row * pitch + col) : own);
+        bst(db.f, cell * sz + q * pb, 0u, (S)f_out);
+        bst(db.g, cell * sz + q * pb, 0u, (S)g_out);
       }
     }
   };
@@ -481,7 +484,7 @@ template <int ST, int BX, int MODE, int PF>
 __global__ __launch_bounds__(BX) void k_tile(Model m, Tiling t, const void *__restrict__ src,
                                              void *__restrict__ dst, int treatment,
                                              unsigned long long *clamp_counter, MomentsOut mo) {
-  __shared__ TileLds<BX> L;
+  __shared__ TileLds<BX, typename Prec<ST>::S> L;
   const int tid = tile_of_block(t);
   if (tid >= t.strips * t.bands) return;
   const int strip = tid % t.strips;
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(BX) void k_batch(const Model *__restrict__ models,
                                               const char *__restrict__ src, char *__restrict__ dst,
                                               int treatment, int nt,
                                               unsigned long long *clamp_counter) {
-  __shared__ TileLds<BX> L;
+  __shared__ TileLds<BX, typename Prec<ST>::S> L;
   const BatchTile bt = tiles[blockIdx.x];
   const Model m = models[bt.lattice];
   const long long off = offs[bt.lattice];
