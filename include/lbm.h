@@ -176,6 +176,54 @@ int lbm_get_tiling(lbm_handle h, int *bx, int *rows);
 int lbm_destroy(lbm_handle h);
 const char *lbm_strerror(int status);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent lattices (sizes and parameters may differ, the
+ * storage precision may not) stepped together, one kernel launch per step
+ * covering every tile of every lattice, optionally replayed from captured
+ * hipGraphs.  Each lattice keeps a single-lattice handle (lbm_batch_lattice)
+ * for initialisation, moments, totals, residuals and checkpoints.  The step
+ * is the same as lbm_step's, node for node, so a lattice advanced in a batch
+ * is bitwise equal to the same lattice advanced alone.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_batch_ctx *lbm_batch_handle;
+
+/* Device bytes for a batch of `count` lattices with parameters p[0..count). */
+int lbm_batch_workspace_bytes(int count, const lbm_params *p, size_t *bytes);
+
+/* Bind a caller-owned workspace and stream; all p[i].precision must agree.
+ * Uploads the lattice tables (synchronous). */
+int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t bytes,
+                     void *hip_stream, lbm_batch_handle *out);
+
+/* Single-lattice handle of lattice i (owned by the batch: do not destroy). */
+int lbm_batch_lattice(lbm_batch_handle b, int i, lbm_handle *out);
+
+/* lbm_init_fields / lbm_moments of lattice i. */
+int lbm_batch_init_fields(lbm_batch_handle b, int i, const double *rho, const double *ux,
+                          const double *uy, const double *T);
+int lbm_batch_moments(lbm_batch_handle b, int i, double *rho, double *ux, double *uy,
+                      double *T);
+
+/* Enqueue n >= 1 steps of every active lattice (all must be initialised). */
+int lbm_batch_step(lbm_batch_handle b, int n, int treatment);
+
+/* Which lattices the next steps advance (active[i] != 0); NULL = all. */
+int lbm_batch_set_active(lbm_batch_handle b, const int *active);
+
+/* Tile shape shared by the batch (bx in 64/128/256 lanes, rows >= 1). */
+int lbm_batch_set_tiling(lbm_batch_handle b, int bx, int rows);
+int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows);
+
+/* k = 0: one eager launch per step.  k even >= 2: lbm_batch_step replays a
+ * hipGraph holding k step launches (captured on first use, recaptured when
+ * the tiling or the active set changes) for every whole k steps. */
+int lbm_batch_use_graph(lbm_batch_handle b, int k);
+
+/* Synchronize and check every lattice (first failing status). */
+int lbm_batch_sync(lbm_batch_handle b);
+
+int lbm_batch_destroy(lbm_batch_handle b);
+
 /* Measurement aid: copy `bytes` (multiple of 16) from src to dst with a
  * plain streaming kernel on `hip_stream`; gives the practical HBM
  * bandwidth ceiling and the copy used to scale byte counters. */

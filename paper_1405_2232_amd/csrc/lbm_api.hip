@@ -7,34 +7,13 @@
 
 #include <new>
 
-#include "../../include/lbm.h"
-#include "lbm_device.h"
+#include "lbm_ctx.h"
 
 using lbmdev::Model;
 using lbmdev::Tiling;
 
-namespace {
+namespace lbmhost {
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Layout {
-  int pitch;
-  long long plane;        // elements
-  size_t elem;            // bytes per stored value
-  size_t dist_bytes;      // one buffer of 18 planes
-  size_t off_buf[2];
-  size_t off_staging;     // 4 dense FP64 planes
-  size_t off_snap;        // 2 dense FP64 planes
-  size_t off_partials;
-  int max_blocks;
-  size_t off_out;         // kPartials doubles
-  size_t off_counters;    // 8 u64
-  size_t total;
-};
-
-long long env_ll(const char *name, long long dflt);
 
 // Default tile shape: wide strips (inner width bx - 2) and bands of 8 rows.
 // Short bands give many blocks (the step is latency-bound at two waves per
@@ -133,6 +112,12 @@ int validate(const lbm_params *p) {
   return LBM_OK;
 }
 
+// the kernels address each half (f or g planes) of a distribution buffer
+// with 32-bit byte offsets
+bool fits_32bit(const Layout &L) {
+  return (unsigned long long)L.plane * L.elem * 9ULL < (1ULL << 32);
+}
+
 Model make_model(const lbm_params *p, const Layout &L) {
   Model m;
   memset(&m, 0, sizeof(m));
@@ -175,32 +160,19 @@ Model make_model(const lbm_params *p, const Layout &L) {
   return m;
 }
 
-}  // namespace
+}  // namespace lbmhost
 
-struct lbm_ctx {
-  lbm_params p;
-  Layout L;
-  Model m;
-  Tiling t;        // step tiling
-  Tiling tm;       // moments tiling (fixed: sizes the partials buffer)
-  int st;          // lbmdev::Storage
-  hipStream_t stream;
-  char *ws;
-  void *buf[2];
-  int cur;
-  double *staging, *snap, *partials, *out;
-  unsigned long long *counters;
-  long long steps;
-  int initialized;
-  int check_every;
-};
+using namespace lbmhost;
+
 
 #define HIPCHK(expr)                        \
   do {                                      \
     if ((expr) != hipSuccess) return LBM_EDEVICE; \
   } while (0)
 
-static int run_moments(lbm_ctx *h, double *rho, double *ux, double *uy, double *T, int write_snap,
+namespace lbmhost {
+
+int run_moments(lbm_ctx *h, double *rho, double *ux, double *uy, double *T, int write_snap,
                        int compare_snap) {
   lbmdev::MomentsOut mo;
   memset(&mo, 0, sizeof(mo));
@@ -219,7 +191,7 @@ static int run_moments(lbm_ctx *h, double *rho, double *ux, double *uy, double *
 }
 
 // read back reductions + clamp counter; synchronizes
-static int fetch_totals(lbm_ctx *h, double red[lbmdev::kPartials], unsigned long long *clamps) {
+int fetch_totals(lbm_ctx *h, double red[lbmdev::kPartials], unsigned long long *clamps) {
   HIPCHK(hipMemcpyAsync(red, h->out, lbmdev::kPartials * sizeof(double), hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipMemcpyAsync(clamps, h->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -228,13 +200,13 @@ static int fetch_totals(lbm_ctx *h, double red[lbmdev::kPartials], unsigned long
   return LBM_OK;
 }
 
-static int status_of(const lbm_ctx *h, const double red[lbmdev::kPartials], unsigned long long clamps) {
+int status_of(const lbm_ctx *h, const double red[lbmdev::kPartials], unsigned long long clamps) {
   if (red[4] > 0.0 || !isfinite(red[0]) || !isfinite(red[1])) return LBM_ENONFINITE;
   if (h->p.psi_policy == 1 && clamps > 0) return LBM_EDOMAIN;
   return LBM_OK;
 }
 
-static int check(lbm_ctx *h) {
+int check(lbm_ctx *h) {
   int rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 0, 0);
   if (rc) return rc;
   double red[lbmdev::kPartials];
@@ -244,13 +216,10 @@ static int check(lbm_ctx *h) {
   return status_of(h, red, clamps);
 }
 
+}  // namespace lbmhost
+
 extern "C" {
 
-// the kernels address each half (f or g planes) of a distribution buffer
-// with 32-bit byte offsets
-static bool fits_32bit(const Layout &L) {
-  return (unsigned long long)L.plane * L.elem * 9ULL < (1ULL << 32);
-}
 
 int lbm_workspace_bytes(const lbm_params *p, size_t *bytes) {
   int rc = validate(p);

@@ -1,0 +1,400 @@
+// Batched stepping of many independent lattices (lbm_batch_* in lbm.h).
+//
+// Every lattice owns a slice of the batch workspace laid out exactly as a
+// single-lattice workspace, with its own lbm_ctx; the batch adds device
+// tables (models, buffer offsets, parities, clamp counters, tiles) and one
+// kernel launch per step that walks the tiles of all active lattices.  Whole
+// groups of k steps can be replayed from a captured hipGraph.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "lbm_ctx.h"
+
+using namespace lbmhost;
+using lbmdev::BatchTables;
+using lbmdev::BatchTile;
+
+struct lbm_batch_ctx {
+  int count;
+  int st;
+  hipStream_t stream;
+  char *ws;
+  std::vector<lbm_ctx *> lat;
+  std::vector<size_t> lat_off;
+  // device tables
+  lbmdev::Model *d_models;
+  long long *d_off0, *d_off1;
+  int *d_phase;
+  unsigned long long **d_clamp;
+  BatchTile *d_tiles;
+  int max_tiles;
+  int ntiles;
+  int bx, rows, pf;
+  std::vector<int> active;
+  std::vector<int> phase;  // host copy: lattice buffer = parity ^ phase
+  int parity;
+  int graph_k;
+  hipStream_t cap;  // private stream the graphs are captured on
+  hipGraphExec_t exec[2];
+  hipGraph_t graph[2];
+  int have_graph[2];
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> lat_off, lat_bytes;
+  size_t off_models, off_off0, off_off1, off_phase, off_clamp, off_tiles;
+  int max_tiles;
+  size_t total;
+};
+
+// tiles of one lattice for lanes bx and band height rows
+int tiles_of(const lbm_params &p, int bx, int rows) {
+  const int strips = (p.nx + bx - 3) / (bx - 2);
+  const int r = rows < p.ny ? rows : p.ny;
+  return strips * ((p.ny + r - 1) / r);
+}
+
+int batch_layout(int count, const lbm_params *p, BatchLayout *B) {
+  if (count < 1 || !p) return LBM_EINVAL;
+  size_t off = 0;
+  B->lat_off.resize(count);
+  B->lat_bytes.resize(count);
+  long long tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    int rc = validate(&p[i]);
+    if (rc) return rc;
+    if (p[i].precision != p[0].precision) return LBM_EINVAL;
+    Layout L;
+    compute_layout(&p[i], &L);
+    if (!fits_32bit(L)) return LBM_EINVAL;
+    B->lat_off[i] = off;
+    B->lat_bytes[i] = L.total;
+    off += align_up(L.total, kAlign);
+    tiles += tiles_of(p[i], 64, 1);  // the most tiles any tiling can need
+  }
+  if (tiles > (1LL << 30)) return LBM_EINVAL;
+  B->max_tiles = (int)tiles;
+  B->off_models = off;
+  off += align_up((size_t)count * sizeof(lbmdev::Model), kAlign);
+  B->off_off0 = off;
+  off += align_up((size_t)count * sizeof(long long), kAlign);
+  B->off_off1 = off;
+  off += align_up((size_t)count * sizeof(long long), kAlign);
+  B->off_phase = off;
+  off += align_up((size_t)count * sizeof(int), kAlign);
+  B->off_clamp = off;
+  off += align_up((size_t)count * sizeof(void *), kAlign);
+  B->off_tiles = off;
+  off += align_up((size_t)B->max_tiles * sizeof(BatchTile), kAlign);
+  B->total = off;
+  return LBM_OK;
+}
+
+void drop_graphs(lbm_batch_ctx *b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->have_graph[k]) {
+      (void)hipGraphExecDestroy(b->exec[k]);
+      (void)hipGraphDestroy(b->graph[k]);
+      b->have_graph[k] = 0;
+    }
+  }
+}
+
+// tile list of the active lattices; consecutive tiles are neighbouring bands
+// of one lattice (the kernel deals them to XCDs in runs); odd bands walk down
+int upload_tiles(lbm_batch_ctx *b) {
+  std::vector<BatchTile> t;
+  t.reserve(b->max_tiles);
+  for (int i = 0; i < b->count; ++i) {
+    if (!b->active[i]) continue;
+    const lbm_params &p = b->lat[i]->p;
+    const int strips = (p.nx + b->bx - 3) / (b->bx - 2);
+    const int rows = b->rows < p.ny ? b->rows : p.ny;
+    const int bands = (p.ny + rows - 1) / rows;
+    for (int band = 0; band < bands; ++band)
+      for (int s = 0; s < strips; ++s) {
+        BatchTile x;
+        memset(&x, 0, sizeof(x));
+        x.lattice = i;
+        x.strip = s;
+        x.band = band;
+        x.rows = rows;
+        x.dir = (band & 1) ? -1 : 1;
+        t.push_back(x);
+      }
+  }
+  if ((int)t.size() > b->max_tiles) return LBM_EINVAL;
+  b->ntiles = (int)t.size();
+  if (!t.empty() && hipMemcpyAsync(b->d_tiles, t.data(), t.size() * sizeof(BatchTile),
+                                   hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+// re-derive each lattice's parity phase from its handle (a member may have
+// been stepped or re-initialised on its own)
+int sync_phases(lbm_batch_ctx *b) {
+  bool changed = false;
+  for (int i = 0; i < b->count; ++i) {
+    const int ph = b->lat[i]->cur ^ b->parity;
+    if (ph != b->phase[i]) {
+      b->phase[i] = ph;
+      changed = true;
+    }
+  }
+  if (!changed) return LBM_OK;
+  if (hipMemcpyAsync(b->d_phase, b->phase.data(), b->count * sizeof(int), hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+BatchTables tables(const lbm_batch_ctx *b) {
+  BatchTables t;
+  t.models = b->d_models;
+  t.off0 = b->d_off0;
+  t.off1 = b->d_off1;
+  t.phase = b->d_phase;
+  t.clamp = b->d_clamp;
+  t.tiles = b->d_tiles;
+  t.ntiles = b->ntiles;
+  t.xcd = 1;
+  return t;
+}
+
+void advance(lbm_batch_ctx *b, int n) {
+  for (int i = 0; i < b->count; ++i)
+    if (b->active[i]) {
+      if (n & 1) b->lat[i]->cur ^= 1;
+      b->lat[i]->steps += n;
+    }
+  if (n & 1) b->parity ^= 1;
+}
+
+// Record graph_k step launches on the private stream (nothing runs); the
+// graph is then replayed on the caller's stream.
+int capture(lbm_batch_ctx *b, int treatment) {
+  const int par = b->parity;
+  if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    b->cap = nullptr;
+    return LBM_EDEVICE;
+  }
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return LBM_EDEVICE;
+  const BatchTables t = tables(b);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < b->graph_k && e == hipSuccess; ++k)
+    e = lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, par ^ (k & 1), treatment, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+  if ((e != hipSuccess || e2 != hipSuccess) && g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess || e2 != hipSuccess) return LBM_EDEVICE;
+  hipGraphExec_t x;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return LBM_EDEVICE;
+  }
+  b->graph[par] = g;
+  b->exec[par] = x;
+  b->have_graph[par] = 1 + treatment;  // remembers the treatment it was captured with
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_workspace_bytes(int count, const lbm_params *p, size_t *bytes) {
+  if (!bytes) return LBM_EINVAL;
+  BatchLayout B;
+  int rc = batch_layout(count, p, &B);
+  if (rc) return rc;
+  *bytes = B.total;
+  return LBM_OK;
+}
+
+int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t bytes,
+                     void *hip_stream, lbm_batch_handle *out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  BatchLayout B;
+  int rc = batch_layout(count, p, &B);
+  if (rc) return rc;
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign) != 0) return LBM_EINVAL;
+  if (bytes < B.total) return LBM_ENOMEM;
+  lbm_batch_ctx *b = new (std::nothrow) lbm_batch_ctx();
+  if (!b) return LBM_ENOMEM;
+  b->count = count;
+  b->stream = (hipStream_t)hip_stream;
+  b->ws = (char *)dev_workspace;
+  b->lat.assign(count, nullptr);
+  b->lat_off = B.lat_off;
+  b->active.assign(count, 1);
+  b->phase.assign(count, 0);
+  b->parity = 0;
+  b->max_tiles = B.max_tiles;
+  b->graph_k = 0;
+  b->cap = nullptr;
+  b->have_graph[0] = b->have_graph[1] = 0;
+  b->d_models = (lbmdev::Model *)(b->ws + B.off_models);
+  b->d_off0 = (long long *)(b->ws + B.off_off0);
+  b->d_off1 = (long long *)(b->ws + B.off_off1);
+  b->d_phase = (int *)(b->ws + B.off_phase);
+  b->d_clamp = (unsigned long long **)(b->ws + B.off_clamp);
+  b->d_tiles = (BatchTile *)(b->ws + B.off_tiles);
+  std::vector<lbmdev::Model> models(count);
+  std::vector<long long> o0(count), o1(count);
+  std::vector<unsigned long long *> cl(count);
+  for (int i = 0; i < count; ++i) {
+    rc = lbm_create(&p[i], b->ws + B.lat_off[i], B.lat_bytes[i], hip_stream, &b->lat[i]);
+    if (rc) {
+      lbm_batch_destroy(b);
+      return rc;
+    }
+    models[i] = b->lat[i]->m;
+    o0[i] = (long long)((char *)b->lat[i]->buf[0] - b->ws);
+    o1[i] = (long long)((char *)b->lat[i]->buf[1] - b->ws);
+    cl[i] = b->lat[i]->counters;
+  }
+  b->st = b->lat[0]->st;
+  // shared tile shape: the batch's widest-lattice default, 8-row bands
+  Tiling t0 = b->lat[0]->t;
+  int maxnx = 0;
+  for (int i = 0; i < count; ++i) maxnx = p[i].nx > maxnx ? p[i].nx : maxnx;
+  b->bx = maxnx >= 192 ? 256 : (maxnx > 62 ? 128 : 64);
+  b->rows = 8;
+  b->pf = t0.pf;
+  hipError_t e = hipMemcpyAsync(b->d_models, models.data(), count * sizeof(lbmdev::Model),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_off0, o0.data(), count * sizeof(long long), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_off1, o1.data(), count * sizeof(long long), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_phase, b->phase.data(), count * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_clamp, cl.data(), count * sizeof(void *), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    lbm_batch_destroy(b);
+    return LBM_EDEVICE;
+  }
+  rc = upload_tiles(b);
+  if (rc) {
+    lbm_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_lattice(lbm_batch_handle b, int i, lbm_handle *out) {
+  if (!b || !out || i < 0 || i >= b->count) return LBM_EINVAL;
+  *out = b->lat[i];
+  return LBM_OK;
+}
+
+int lbm_batch_init_fields(lbm_batch_handle b, int i, const double *rho, const double *ux,
+                          const double *uy, const double *T) {
+  if (!b || i < 0 || i >= b->count) return LBM_EINVAL;
+  return lbm_init_fields(b->lat[i], rho, ux, uy, T);
+}
+
+int lbm_batch_moments(lbm_batch_handle b, int i, double *rho, double *ux, double *uy, double *T) {
+  if (!b || i < 0 || i >= b->count) return LBM_EINVAL;
+  return lbm_moments(b->lat[i], rho, ux, uy, T);
+}
+
+int lbm_batch_step(lbm_batch_handle b, int n, int treatment) {
+  if (!b || n < 1) return LBM_EINVAL;
+  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  for (int i = 0; i < b->count; ++i)
+    if (b->active[i] && !b->lat[i]->initialized) return LBM_ESTATE;
+  int rc = sync_phases(b);
+  if (rc) return rc;
+  if (b->ntiles == 0) return LBM_OK;
+  while (b->graph_k >= 2 && n >= b->graph_k) {
+    const int par = b->parity;
+    if (b->have_graph[par] && b->have_graph[par] != 1 + treatment) {
+      (void)hipGraphExecDestroy(b->exec[par]);
+      (void)hipGraphDestroy(b->graph[par]);
+      b->have_graph[par] = 0;
+    }
+    if (!b->have_graph[par]) {
+      rc = capture(b, treatment);
+      if (rc) return rc;
+    }
+    if (hipGraphLaunch(b->exec[par], b->stream) != hipSuccess) return LBM_EDEVICE;
+    advance(b, b->graph_k);
+    n -= b->graph_k;
+  }
+  const BatchTables t = tables(b);
+  for (int k = 0; k < n; ++k) {
+    if (lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, b->parity, treatment, b->stream) !=
+        hipSuccess)
+      return LBM_EDEVICE;
+    advance(b, 1);
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_set_active(lbm_batch_handle b, const int *active) {
+  if (!b) return LBM_EINVAL;
+  for (int i = 0; i < b->count; ++i) b->active[i] = active ? (active[i] != 0) : 1;
+  return upload_tiles(b);
+}
+
+int lbm_batch_set_tiling(lbm_batch_handle b, int bx, int rows) {
+  if (!b) return LBM_EINVAL;
+  if (bx != 64 && bx != 128 && bx != 256) return LBM_EINVAL;
+  if (rows < 1) return LBM_EINVAL;
+  b->bx = bx;
+  b->rows = rows;
+  return upload_tiles(b);
+}
+
+int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows) {
+  if (!b || !bx || !rows) return LBM_EINVAL;
+  *bx = b->bx;
+  *rows = b->rows;
+  return LBM_OK;
+}
+
+int lbm_batch_use_graph(lbm_batch_handle b, int k) {
+  if (!b || k < 0 || k == 1 || (k & 1)) return LBM_EINVAL;
+  if (k != b->graph_k) drop_graphs(b);
+  b->graph_k = k;
+  return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch_handle b) {
+  if (!b) return LBM_EINVAL;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
+  for (int i = 0; i < b->count; ++i) {
+    if (!b->lat[i]->initialized) continue;
+    const int rc = lbm_sync(b->lat[i]);
+    if (rc) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch_handle b) {
+  if (!b) return LBM_EINVAL;
+  drop_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (lbm_ctx *h : b->lat)
+    if (h) lbm_destroy(h);
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -86,16 +86,25 @@ __host__ __device__ inline size_t ref_plane_offset(const Model &m, int st) {
   return st == ST_F64 ? 0 : (size_t)18 * (size_t)m.plane * sizeof(float);
 }
 
-// Batched step: many lattices, one launch.  Device tables: models[L],
-// offs[L] (byte offsets of each lattice in the two buffers), tiles[nblocks].
+// Batched step: many lattices, one launch.  Device tables, one entry per
+// lattice: its model, the byte offsets (from `base`) of its two distribution
+// buffers, the parity of the buffer that holds its current state relative to
+// the batch-wide step parity, and its psi-clamp counter; plus the tile list.
 struct BatchTile {
   int lattice, strip, band, rows;
-  int dir;    // +1 up, -1 down
+  int dir;  // +1 up, -1 down
   int pad[3];
 };
-hipError_t launch_batch_step(const Model *d_models, const long long *d_offsets,
-                             const BatchTile *d_tiles, int ntiles, int bx, int pf, int st,
-                             const void *src, void *dst, int treatment,
-                             unsigned long long *clamp_counter, hipStream_t s);
+struct BatchTables {
+  const Model *models;
+  const long long *off0, *off1;
+  const int *phase;
+  unsigned long long *const *clamp;
+  const BatchTile *tiles;
+  int ntiles;
+  int xcd;
+};
+hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char *base, int parity,
+                             int treatment, hipStream_t s);
 
 }  // namespace lbmdev

@@ -497,21 +497,25 @@ __global__ __launch_bounds__(BX) void k_tile(Model m, Tiling t, const void *__re
 }
 
 template <int ST, int BX, int PF>
-__global__ __launch_bounds__(BX) void k_batch(const Model *__restrict__ models,
-                                              const long long *__restrict__ offs,
-                                              const BatchTile *__restrict__ tiles,
-                                              const char *__restrict__ src, char *__restrict__ dst,
-                                              int treatment, int nt,
-                                              unsigned long long *clamp_counter) {
+__global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__ base, int parity,
+                                              int treatment) {
   __shared__ TileLds<BX, typename Prec<ST>::S> L;
-  const BatchTile bt = tiles[blockIdx.x];
-  const Model m = models[bt.lattice];
-  const long long off = offs[bt.lattice];
-  const int y0 = bt.band * bt.rows;
-  const int y1 = min(y0 + bt.rows, m.ny);
+  int tid = blockIdx.x;
+  if (bt.xcd) {
+    const int per = (int)gridDim.x >> 3;
+    tid = (tid & 7) * per + (tid >> 3);
+  }
+  if (tid >= bt.ntiles) return;
+  const BatchTile t = bt.tiles[tid];
+  const Model m = bt.models[t.lattice];
+  const int sb = parity ^ bt.phase[t.lattice];
+  char *src = base + (sb ? bt.off1[t.lattice] : bt.off0[t.lattice]);
+  char *dst = base + (sb ? bt.off0[t.lattice] : bt.off1[t.lattice]);
+  const int y0 = t.band * t.rows;
+  const int y1 = min(y0 + t.rows, m.ny);
   MomentsOut mo{};
-  tile<ST, BX, MODE_STEP, PF>(m, src + off, dst + off, bt.strip, y0, y1, bt.dir, nt, treatment,
-                              clamp_counter, mo, L, blockIdx.x);
+  tile<ST, BX, MODE_STEP, PF>(m, src, dst, t.strip, y0, y1, t.dir, 0, treatment, bt.clamp[t.lattice],
+                              mo, L, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,17 +744,14 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(const Model *d_models, const long long *d_offsets,
-                             const BatchTile *d_tiles, int ntiles, int bx, int pf, int st,
-                             const void *src, void *dst, int treatment,
-                             unsigned long long *cc, hipStream_t s) {
-  const dim3 g((unsigned)ntiles);
-  const char *sp = (const char *)src;
-  char *dp = (char *)dst;
-  const int nt = 0;
-#define LBM_B(ST_, B_, PF_)                                                                      \
-  hipLaunchKernelGGL((k_batch<ST_, B_, PF_>), g, dim3(B_), 0, s, d_models, d_offsets, d_tiles, sp, \
-                     dp, treatment, nt, cc)
+hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char *base, int parity,
+                             int treatment, hipStream_t s) {
+  unsigned grid = (unsigned)t.ntiles;
+  if (t.xcd) grid = (grid + 7u) & ~7u;
+  if (grid == 0) return hipSuccess;
+  const dim3 g(grid);
+#define LBM_B(ST_, B_, PF_) \
+  hipLaunchKernelGGL((k_batch<ST_, B_, PF_>), g, dim3(B_), 0, s, t, base, parity, treatment)
 #define LBM_BX(ST_, PF_)                      \
   do {                                        \
     if (bx == 64) LBM_B(ST_, 64, PF_);        \
@@ -759,7 +760,7 @@ hipError_t launch_batch_step(const Model *d_models, const long long *d_offsets,
     else return hipErrorInvalidValue;         \
   } while (0)
   if (st == ST_F64) {
-    LBM_BX(ST_F64, 1);
+    if (pf >= 2) LBM_BX(ST_F64, 2); else LBM_BX(ST_F64, 1);
   } else if (st == ST_F32_GLOBAL) {
     if (pf >= 2) LBM_BX(ST_F32_GLOBAL, 2); else LBM_BX(ST_F32_GLOBAL, 1);
   } else if (st == ST_F32_LOCAL) {

@@ -198,10 +198,18 @@ def wall_slab(nx=2048, ny=2048, T_ratio=0.85, T_bottom_ratio=0.80, T_top_ratio=0
 _SIDES = np.arange(64, 513, 32)
 
 
-def batch_lattices(count=256, seed=2):
+# Stable range of the static droplet with these EOS constants and Guo
+# forcing: below about 0.80 T_c (density ratio above ~14) or with tau_f
+# under ~0.7 the pseudopotential model diverges within a few hundred steps.
+STABLE_T_RATIO = (0.82, 0.95)
+STABLE_TAU_F = (0.7, 1.2)
+
+
+def batch_lattices(count=256, seed=2, t_ratio=STABLE_T_RATIO, tau_f_range=STABLE_TAU_F):
     """Uneven batch of periodic static droplets: sides uniform in
-    {64, 96, ..., 512}, radius U[0.15, 0.35] min side, T0/T_c U[0.70, 0.95],
-    tau_f and tau_g U[0.6, 1.2]; +-1% / +-0.5% noise."""
+    {64, 96, ..., 512}, radius U[0.15, 0.35] min side, T0/T_c and tau_f
+    uniform in the model's stable range (0.82-0.95, 0.7-1.2), tau_g
+    U[0.6, 1.2]; +-1% / +-0.5% noise."""
     rng = _rng(seed)
     Tc = cs_tc()
     out = []
@@ -209,8 +217,8 @@ def batch_lattices(count=256, seed=2):
         nx = int(rng.choice(_SIDES))
         ny = int(rng.choice(_SIDES))
         R = rng.uniform(0.15, 0.35) * min(nx, ny)
-        tr = rng.uniform(0.70, 0.95)
-        tau_f = rng.uniform(0.6, 1.2)
+        tr = rng.uniform(*t_ratio)
+        tau_f = rng.uniform(*tau_f_range)
         tau_g = rng.uniform(0.6, 1.2)
         T0 = tr * Tc
         rv, rl = maxwell_densities(T0)
@@ -220,16 +228,18 @@ def batch_lattices(count=256, seed=2):
     return out
 
 
-def random_droplets_with_gradient(seed, n=256, rmin=8.0, rmax=48.0, max_drops=6):
+def random_droplets_with_gradient(seed, n=256, rmin=8.0, rmax=48.0, max_drops=6,
+                                  t_ratio=STABLE_T_RATIO, tau_f_range=STABLE_TAU_F):
     """Warm-start training/evaluation case: 1-6 droplets of radius 8-48 in an
     n x n box, periodic in x, walls in y holding a linear temperature
-    difference dT in [0, 0.1 T_c]; T0/T_c in [0.70, 0.95]; tau in [0.6, 1.2]."""
+    difference dT in [0, 0.1 T_c]; T0/T_c and tau_f in the model's stable
+    range; tau_g in [0.6, 1.2]."""
     rng = _rng(seed)
     Tc = cs_tc()
-    tr = rng.uniform(0.70, 0.95)
+    tr = rng.uniform(*t_ratio)
     dT = rng.uniform(0.0, 0.1) * Tc
     T0 = tr * Tc
-    tau_f = rng.uniform(0.6, 1.2)
+    tau_f = rng.uniform(*tau_f_range)
     tau_g = rng.uniform(0.6, 1.2)
     k = int(rng.integers(1, max_drops + 1))
     rv, rl = maxwell_densities(T0)

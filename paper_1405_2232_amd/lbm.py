@@ -88,6 +88,18 @@ def lib():
             "lbm_get_tiling": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
             "lbm_destroy": [vp],
             "lbm_copy_probe": [vp, vp, sz, vp],
+            "lbm_batch_workspace_bytes": [i, P, ctypes.POINTER(sz)],
+            "lbm_batch_create": [i, P, vp, sz, vp, ctypes.POINTER(vp)],
+            "lbm_batch_lattice": [vp, i, ctypes.POINTER(vp)],
+            "lbm_batch_init_fields": [vp, i, dp, dp, dp, dp],
+            "lbm_batch_moments": [vp, i, dp, dp, dp, dp],
+            "lbm_batch_step": [vp, i, i],
+            "lbm_batch_set_active": [vp, ctypes.POINTER(i)],
+            "lbm_batch_set_tiling": [vp, i, i],
+            "lbm_batch_get_tiling": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
+            "lbm_batch_use_graph": [vp, i],
+            "lbm_batch_sync": [vp],
+            "lbm_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -149,40 +161,8 @@ def workspace_bytes(cfg, precision="fp64", rho_ref=None, T_ref=None):
     return n.value
 
 
-class Lattice:
-    """One lattice on the GPU.  `precision` is "fp64", "fp32dev" (global
-    deviation shifts) or "fp32local" (per-node density shift); rho_ref and
-    T_ref default to the mean initial density and temperature (set at
-    init_fields unless given here)."""
-
-    def __init__(self, cfg, precision="fp64", rho_ref=None, T_ref=None, device=None, stream=None):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("liblbm needs a ROCm GPU; none is visible")
-        self.cfg = dict(cfg)
-        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
-        self.precision = precision
-        self._rho_ref, self._T_ref = rho_ref, T_ref
-        self.device = torch.device(device if device is not None else "cuda")
-        self._stream = stream
-        self._h = None
-        self.ws = None
-
-    # creation is deferred to init_fields when the deviation shifts come
-    # from the initial fields
-    def _create(self, rho_ref, T_ref):
-        import torch
-        self.close()
-        self._p = make_params(self.cfg, self.precision, rho_ref, T_ref)
-        n = ctypes.c_size_t()
-        _chk("lbm_workspace_bytes", lib().lbm_workspace_bytes(ctypes.byref(self._p), ctypes.byref(n)))
-        self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
-        s = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
-        self.stream = s
-        h = ctypes.c_void_p()
-        _chk("lbm_create", lib().lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.ws.data_ptr()),
-                                            n.value, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
-        self._h = h
+class _HandleOps:
+    """Calls on one lattice handle (owned by a Lattice or by a Batch)."""
 
     @property
     def n(self):
@@ -192,16 +172,11 @@ class Lattice:
     def handle(self):
         return self._h
 
-    def init_fields(self, rho, T, ux=None, uy=None):
+    def _init(self, rho, T, ux=None, uy=None):
         n = self.n
         r, t = _host(rho, n), _host(T, n)
         u = _host(ux, n) if ux is not None else None
         v = _host(uy, n) if uy is not None else None
-        rho_ref = self._rho_ref if self._rho_ref is not None else float(r.mean())
-        T_ref = self._T_ref if self._T_ref is not None else float(t.mean())
-        if self._h is None or (self.precision != "fp64" and
-                               (rho_ref != self._p.rho_ref or T_ref != self._p.T_ref)):
-            self._create(rho_ref, T_ref)
         _chk("lbm_init_fields", lib().lbm_init_fields(self._h, _dp(r), _dp(u) if u is not None else None,
                                                       _dp(v) if v is not None else None, _dp(t)))
 
@@ -262,9 +237,139 @@ class Lattice:
         _chk("lbm_get_tiling", lib().lbm_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+
+class Lattice(_HandleOps):
+    """One lattice on the GPU.  `precision` is "fp64", "fp32dev" (global
+    deviation shifts) or "fp32local" (per-node density shift); rho_ref and
+    T_ref default to the mean initial density and temperature (set at
+    init_fields unless given here)."""
+
+    def __init__(self, cfg, precision="fp64", rho_ref=None, T_ref=None, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a ROCm GPU; none is visible")
+        self.cfg = dict(cfg)
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        self.precision = precision
+        self._rho_ref, self._T_ref = rho_ref, T_ref
+        self.device = torch.device(device if device is not None else "cuda")
+        self._stream = stream
+        self._h = None
+        self.ws = None
+
+    # creation is deferred to init_fields when the deviation shifts come
+    # from the initial fields
+    def _create(self, rho_ref, T_ref):
+        import torch
+        self.close()
+        self._p = make_params(self.cfg, self.precision, rho_ref, T_ref)
+        n = ctypes.c_size_t()
+        _chk("lbm_workspace_bytes", lib().lbm_workspace_bytes(ctypes.byref(self._p), ctypes.byref(n)))
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        s = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        h = ctypes.c_void_p()
+        _chk("lbm_create", lib().lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self.ws.data_ptr()),
+                                            n.value, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def init_fields(self, rho, T, ux=None, uy=None):
+        r, t = _host(rho, self.n), _host(T, self.n)
+        rho_ref = self._rho_ref if self._rho_ref is not None else float(r.mean())
+        T_ref = self._T_ref if self._T_ref is not None else float(t.mean())
+        if self._h is None or (self.precision != "fp64" and
+                               (rho_ref != self._p.rho_ref or T_ref != self._p.T_ref)):
+            self._create(rho_ref, T_ref)
+        self._init(r, t, ux, uy)
+
     def close(self):
         if self._h is not None:
             lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Member(_HandleOps):
+    def __init__(self, batch, i, h, nx, ny):
+        self._batch = batch  # keeps the batch (and its workspace) alive
+        self.i = i
+        self._h = h
+        self.nx, self.ny = nx, ny
+
+    def init_fields(self, rho, T, ux=None, uy=None):
+        self._init(rho, T, ux, uy)
+
+
+class Batch:
+    """Many lattices stepped together.  `cfgs` is a list of parameter dicts
+    (sizes and parameters may differ); `refs` optionally gives (rho_ref,
+    T_ref) per lattice for the FP32 storage forms."""
+
+    def __init__(self, cfgs, precision="fp64", refs=None, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a ROCm GPU; none is visible")
+        self.count = len(cfgs)
+        refs = refs if refs is not None else [(None, None)] * self.count
+        P = (Params * self.count)()
+        for i, c in enumerate(cfgs):
+            P[i] = make_params(c, precision, refs[i][0], refs[i][1])
+        self._P = P
+        n = ctypes.c_size_t()
+        _chk("lbm_batch_workspace_bytes", lib().lbm_batch_workspace_bytes(self.count, P, ctypes.byref(n)))
+        dev = torch.device(device if device is not None else "cuda")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = s
+        h = ctypes.c_void_p()
+        _chk("lbm_batch_create", lib().lbm_batch_create(self.count, P, ctypes.c_void_p(self.ws.data_ptr()),
+                                                        n.value, ctypes.c_void_p(s.cuda_stream),
+                                                        ctypes.byref(h)))
+        self._h = h
+        self.members = []
+        for i, c in enumerate(cfgs):
+            m = ctypes.c_void_p()
+            _chk("lbm_batch_lattice", lib().lbm_batch_lattice(h, i, ctypes.byref(m)))
+            self.members.append(_Member(self, i, m, int(c["nx"]), int(c["ny"])))
+
+    def __getitem__(self, i):
+        return self.members[i]
+
+    def __len__(self):
+        return self.count
+
+    def step(self, n, treatment):
+        _chk("lbm_batch_step", lib().lbm_batch_step(self._h, int(n), int(treatment)))
+
+    def set_active(self, active=None):
+        if active is None:
+            _chk("lbm_batch_set_active", lib().lbm_batch_set_active(self._h, None))
+        else:
+            a = (ctypes.c_int * self.count)(*[int(bool(x)) for x in active])
+            _chk("lbm_batch_set_active", lib().lbm_batch_set_active(self._h, a))
+
+    def set_tiling(self, bx, rows):
+        _chk("lbm_batch_set_tiling", lib().lbm_batch_set_tiling(self._h, int(bx), int(rows)))
+
+    def get_tiling(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _chk("lbm_batch_get_tiling", lib().lbm_batch_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def use_graph(self, k):
+        _chk("lbm_batch_use_graph", lib().lbm_batch_use_graph(self._h, int(k)))
+
+    def sync(self):
+        return lib().lbm_batch_sync(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().lbm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

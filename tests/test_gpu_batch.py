@@ -1,0 +1,148 @@
+"""Batched stepping: one launch per step over many uneven lattices (and
+hipGraph replays of it) gives, lattice by lattice, exactly the state the
+single-lattice path gives, and the sampled lattices match the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import FP32_RHO_REL, FP32_T_ABS, FP64_TOL, need_gpu, say
+from oracle import CORRECTED, PLAIN, Oracle
+from paper_1405_2232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _small_batch(count=10, seed=7):
+    """Uneven droplets: sides 40..300, different tau, T0, walls on some."""
+    rng = np.random.default_rng(seed)
+    Tc = inputs.cs_tc()
+    out = []
+    for k in range(count):
+        nx = int(rng.integers(40, 300))
+        ny = int(rng.integers(20, 200))
+        p, rho, T = inputs.static_droplet(nx=nx, ny=ny, radius=0.25 * min(nx, ny),
+                                          T_ratio=float(rng.uniform(0.82, 0.92)),
+                                          tau_f=float(rng.uniform(0.7, 1.2)),
+                                          tau_g=float(rng.uniform(0.6, 1.2)), seed=100 + k)
+        if k % 3 == 1:
+            p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc, gy=-1e-5)
+        out.append((p, rho, T))
+    return out
+
+
+def _refs(cases):
+    return [(float(r.mean()), float(t.mean())) for _, r, t in cases]
+
+
+def _single_states(cases, precision, steps, treatment):
+    from paper_1405_2232_amd.lbm import Lattice
+    states = []
+    for (p, rho, T), ref in zip(cases, _refs(cases)):
+        g = Lattice(p, precision, rho_ref=ref[0], T_ref=ref[1])
+        g.init_fields(rho, T)
+        if steps:
+            g.step(steps, treatment)
+        states.append(g.get_state())
+    return states
+
+
+def _batch(cases, precision):
+    from paper_1405_2232_amd.lbm import Batch
+    b = Batch([c[0] for c in cases], precision, refs=_refs(cases))
+    for m, (p, rho, T) in zip(b.members, cases):
+        m.init_fields(rho, T)
+    return b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local", "fp32dev"])
+def test_batch_equals_single_lattice_bitwise(precision):
+    cases = _small_batch()
+    ref = _single_states(cases, precision, 57, CORRECTED)
+    for tiling in (None, (64, 4), (128, 8), (256, 16)):
+        say("case batch", precision, tiling)
+        b = _batch(cases, precision)
+        if tiling:
+            b.set_tiling(*tiling)
+        b.step(57, CORRECTED)
+        for i, m in enumerate(b.members):
+            assert np.array_equal(m.get_state(), ref[i]), (tiling, i)
+        b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+def test_batch_graph_replays_match_eager(precision):
+    """Graph replays interleaved with eager steps and host syncs; every
+    replay's result is checked against an eagerly stepped twin."""
+    import torch
+    cases = _small_batch(6, seed=9)
+    eager = _batch(cases, precision)
+    graph = _batch(cases, precision)
+    graph.use_graph(8)
+    done = 0
+    for chunk in (16, 3, 8, 8, 5, 24):
+        graph.step(chunk, PLAIN if done % 2 else CORRECTED)
+        eager.step(chunk, PLAIN if done % 2 else CORRECTED)
+        done += chunk
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert np.array_equal(graph[i].get_state(), eager[i].get_state()), (chunk, i)
+    assert graph[0].totals()[6] == done
+
+
+def test_batch_active_mask_and_member_steps():
+    """Frozen lattices keep their state; a member stepped on its own keeps
+    its own step parity inside the batch."""
+    cases = _small_batch(5, seed=11)
+    b = _batch(cases, "fp64")
+    b.step(10, CORRECTED)
+    b.set_active([1, 0, 1, 0, 1])
+    b.step(7, CORRECTED)
+    b[3].step(3, CORRECTED)  # member stepped alone
+    b.set_active(None)
+    b.step(6, CORRECTED)
+    expect = [23, 16, 23, 19, 23]
+    for i, (p, rho, T) in enumerate(cases):
+        ref = _single_states([(p, rho, T)], "fp64", expect[i], CORRECTED)[0]
+        assert np.array_equal(b[i].get_state(), ref), i
+        assert b[i].totals()[6] == expect[i]
+
+
+@pytest.mark.parametrize("precision", ["fp32local", "fp64"])
+def test_batch_256_uneven_lattices(precision):
+    """The 256-lattice batch (sides 64..512, seed 2) in the benchmark's
+    launch shape: sampled lattices against the oracle, and every lattice's
+    mass conserved."""
+    import torch
+    cases = inputs.batch_lattices()
+    say("case batch256", precision, sum(p["nx"] * p["ny"] for p, _, _ in cases), "nodes")
+    b = _batch(cases, precision)
+    b.use_graph(10)
+    m0 = [b[i].totals()[0] for i in range(len(cases))]
+    steps = 40
+    b.step(steps, CORRECTED)
+    torch.cuda.synchronize()
+    assert b.sync() == 0
+    for i in range(len(cases)):
+        m1 = b[i].totals()[0]
+        tol = 1e-12 if precision == "fp64" else 1e-9
+        assert abs(m1 - m0[i]) <= tol * m0[i], i
+    rng = np.random.default_rng(0)
+    for i in sorted(rng.choice(len(cases), 4, replace=False)):
+        p, rho, T = cases[i]
+        o = Oracle(p)
+        o.init_fields(rho, T)
+        o.step(steps, CORRECTED)
+        mo, mg = o.moments(), b[i].moments()
+        if precision == "fp64":
+            e = max(float(np.abs(a - c).max()) for a, c in zip(mg, mo))
+            say("batch256 lattice", i, p["nx"], p["ny"], e)
+            assert e <= FP64_TOL
+        else:
+            rr = float(np.max(np.abs(mg[0] - mo[0]) / mo[0]))
+            ta = float(np.abs(mg[3] - mo[3]).max())
+            say("batch256 lattice", i, p["nx"], p["ny"], rr, ta)
+            assert rr <= FP32_RHO_REL and ta <= FP32_T_ABS
