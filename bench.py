@@ -52,14 +52,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the FP64/FP32-global side runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-lattice batch section")
+    ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
     return ap.parse_args()
 
 
-def copy_probe_only(nbytes):
+def copy_rate(nbytes):
     """Ten launches of the plain streaming copy over `nbytes`: the reference
-    for scaling byte counters and the practical bandwidth ceiling."""
+    for scaling byte counters and the practical bandwidth ceiling.
+    Returns (ms per copy, GB/s counting read + write)."""
     import torch
     from paper_1405_2232_amd.lbm import copy_probe
     a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
@@ -74,8 +77,72 @@ def copy_probe_only(nbytes):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 10
-    print(json.dumps({"copy_bytes": nbytes, "ms": round(ms, 5),
-                      "GBs": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+    del a, b
+    return ms, 2 * nbytes / ms / 1e6
+
+
+def copy_probe_only(nbytes):
+    ms, gbs = copy_rate(nbytes)
+    print(json.dumps({"copy_bytes": nbytes, "ms": round(ms, 5), "GBs": round(gbs, 1)}), flush=True)
+
+
+def batch_section(steps, torch):
+    """The 256 uneven periodic droplet lattices (sides 64..512, seed 2):
+    every lattice advanced `steps` steps by one launch per step replayed
+    from hipGraphs, FP32 per-node-reference storage, autotuned tile shape;
+    against the same lattices advanced one after another by single-lattice
+    FP64 launches (timed over fewer steps per lattice and scaled: the cost
+    per step is constant)."""
+    from paper_1405_2232_amd import autotune, inputs
+    from paper_1405_2232_amd.lbm import CORRECTED, Batch, Lattice
+    cases = inputs.batch_lattices()
+    cells = sum(p["nx"] * p["ny"] for p, _, _ in cases)
+    refs = [(float(r.mean()), float(t.mean())) for _, r, t in cases]
+
+    def make():
+        b = Batch([c[0] for c in cases], "fp32local", refs=refs)
+        for m, (p, rho, T) in zip(b.members, cases):
+            m.init_fields(rho, T)
+        return b
+
+    sizes = [(p["nx"], p["ny"]) for p, _, _ in cases]
+    (bx, rows), tried = autotune.tune(make, "batch", "fp32local", sizes, CORRECTED)
+    b = make()
+    b.set_tiling(bx, rows)
+    b.use_graph(10)
+    b.step(50, CORRECTED)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    b.step(steps, CORRECTED)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = b.sync()
+    if status != 0:
+        raise SystemExit("the batch reported status %d" % status)
+    batch_ms = e0.elapsed_time(e1)
+    del b
+
+    seq_steps = 100
+    seq_ms = 0.0
+    for (p, rho, T) in cases:
+        g = Lattice(p, "fp64")
+        g.init_fields(rho, T)
+        g.step(10, CORRECTED)
+        seq_ms += timed_steps(g, seq_steps, CORRECTED, torch) * steps
+        del g
+    return {"lattices": len(cases), "nodes": cells, "steps": steps,
+            "fp32local_graph_s": round(batch_ms / 1e3, 3), "wall_s": round(wall, 3),
+            "mlups": round(cells * steps / (batch_ms / 1e3) / 1e6, 1),
+            "tile": [bx, rows], "autotune_ms_per_step": tried,
+            "sequential_fp64_s": round(seq_ms / 1e3, 3),
+            "sequential_fp64_mlups": round(cells * steps / (seq_ms / 1e3) / 1e6, 1),
+            "speedup": round(seq_ms / batch_ms, 2),
+            "sequential_note": "single-lattice FP64 launches, %d timed steps per lattice, scaled to %d"
+                               % (seq_steps, steps)}
 
 
 def timed_steps(g, steps, treatment, torch):
@@ -166,6 +233,8 @@ def main():
                 and tr.get("nx") == args.nx and tr.get("ny") == args.ny:
             traffic = tr.get("bytes_per_launch")
 
+    copy_ms, copy_gbs = copy_rate(1 << 30)
+
     extra = {}
     if not args.no_extra:
         for prec in ("fp64", "fp32dev"):
@@ -203,9 +272,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
-                     "bytes_per_node": ALG_BYTES[args.precision]},
+                     "bytes_per_node": ALG_BYTES[args.precision],
+                     "copy_GBs": round(copy_gbs, 1)},
         "by_precision": extra,
     }
+    if not args.no_batch:
+        line["batched"] = batch_section(args.batch_steps, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, rho, T, treatment, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -53,10 +53,10 @@ class Params(ctypes.Structure):
 _lib = None
 
 
-def header_functions():
-    """Names of the functions include/lbm.h declares."""
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char|void)\s*\*?\s*(lbm_\w+)\s*\(", txt, re.M)))
+def header_functions(header=HEADER):
+    """Names of the functions a header under include/ declares."""
+    txt = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char|void)\s*\*?\s*(lbm\w*_\w+)\s*\(", txt, re.M)))
 
 
 def lib():

@@ -10,10 +10,35 @@ from paper_1405_2232_amd import inputs, lbm
 
 def test_library_exports_every_declared_symbol():
     names = lbm.header_functions()
-    assert len(names) >= 17
+    assert len(names) >= 31
     L = ctypes.CDLL(lbm.LIB_PATH)
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
+
+
+def test_library_exports_every_network_symbol():
+    import os
+    names = lbm.header_functions(os.path.join(os.path.dirname(lbm.HEADER), "lbmnn.h"))
+    assert len(names) == 16, names
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_network_argument_checks_without_gpu():
+    """Bad sizes and alignments are rejected before any launch."""
+    from paper_1405_2232_amd import nn
+    L = nn.lib()
+    # channel counts not multiples of 16, odd pooling sizes, bad strides
+    assert L.lbmnn_conv3x3(8, 16, 0, None, 0, 0, 8, None, 8, 16, 0, 1, 4, 4, 12, 16, 1, 1, None) == -1
+    assert L.lbmnn_conv3x3(8, 16, 0, None, 0, 0, 8, None, 8, 16, 8, 1, 4, 4, 16, 16, 1, 1, None) == -1
+    assert L.lbmnn_conv3x3(8, 16, 0, None, 0, 0, 8, None, 8, 16, 0, 1, 4, 4, 16, 144, 1, 1, None) == -1
+    assert L.lbmnn_conv3x3_wgrad(8, 128, 0, 8, 128, 0, None, 0, 0, 8, None, 8, 1, 4, 4, 128, 128, 1, None) == -1
+    assert L.lbmnn_pool2(8, 16, 0, 8, 16, 0, 1, 5, 4, 16, None) == -1
+    assert L.lbmnn_conv3x3(4, 16, 0, None, 0, 0, 8, None, 8, 16, 0, 1, 4, 4, 16, 16, 1, 1, None) == -1
+    assert L.lbmnn_head(8, 32, 0, 8, 8, 8, 8, 1, 4, 4, 24, None) == -1
+    assert L.lbmnn_adam(8, 8, 8, 8, 8, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1
+    assert L.lbmnn_wgrad_partials(1, 4, 4, 16, 16) > 0
 
 
 def test_header_and_binding_struct_agree():
