@@ -54,10 +54,10 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
-        for name in ("lbmnn_wgrad_partials", "lbmnn_head_partials"):
-            fn = getattr(L, name)
-            fn.argtypes = [i, i, i, i, i]
-            fn.restype = sz
+        L.lbmnn_wgrad_partials.argtypes = [i, i, i, i, i]
+        L.lbmnn_wgrad_partials.restype = sz
+        L.lbmnn_head_partials.argtypes = [i, i, i, i]
+        L.lbmnn_head_partials.restype = sz
         _sig_done = True
     return L
 
