@@ -23,6 +23,11 @@
  *      plus C_i of Eq. (25) for the corrected equation, Eq. (24).
  *   7. f_i(x + e_i, t + 1) = f_i*(x), the same for g.
  *
+ * The third treatment (LBMREF_FD_RK2) replaces steps 6-7 for g by the
+ * finite-difference solution of the temperature equation, Eq. (26), with
+ * the two-stage Runge-Kutta scheme of Eq. (27); the temperature is then
+ * carried as g_i = cv T f_i (so that sum_i g_i = rho cv T still holds).
+ *
  * Readings where the paper is silent:
  *   - F_i is the forcing term of Guo et al. (the paper cites it as [21]):
  *     F_i = (1 - 1/(2 tau_f)) w_i [(e_i - u)/c_s^2 + (e_i.u) e_i / c_s^4] . F
@@ -31,6 +36,17 @@
  *   - psi^2 < 0 (outside the EOS domain of a real psi) clamps psi to 0 and
  *     is counted; with beta = 0 only psi^2 enters Eq. (4) and nothing is
  *     clamped;
+ *   - Eq. (27) as printed evaluates h2 at T^n + (dt/2) h1 but averages
+ *     h1 and h2 with weight dt/2, which is not a second-order pair; it is
+ *     read as Heun's method, h2 = K(T^n + dt h1), keeping the printed
+ *     average.  The isotropic central differences of Eq. (26) are
+ *     grad phi = sum_i w(|e_i|^2) phi(x + e_i) e_i and
+ *     lap phi = 2 sum_i w(|e_i|^2) (phi(x + e_i) - phi(x)), with
+ *     div(lambda grad T) = lambda lap T + grad lambda . grad T and
+ *     lambda = (tau_g - 1/2) cv rho c_s^2 (the conductivity stated after
+ *     Eq. (23)); u and rho are those of time t for both stages.  Beyond a
+ *     Dirichlet wall the temperature ghost is 2 T_w - T(boundary node),
+ *     beyond an adiabatic wall T(boundary node); rho mirrors;
  *   - walls sit halfway between nodes; f bounces back; g bounces back
  *     (adiabatic) or anti-bounces back with the wall value rho(x) cv T_w
  *     (Dirichlet); the pseudopotential ghost beyond a wall mirrors the
@@ -69,6 +85,7 @@ struct lbmref_ctx {
   long n;
   double *f, *g, *f2, *g2;   /* [9][ny][nx] */
   double *rho, *jx, *jy, *E, *T, *psi, *psi2;
+  double *ux, *uy, *K1, *K2, *Ts; /* FD treatment: velocity, stages */
   long clamp_count;
   long step;
   int have_fields;
@@ -178,8 +195,13 @@ int lbmref_create(const lbmref_params *p, lbmref_handle *out) {
   h->T = (double *)malloc(fld);
   h->psi = (double *)malloc(fld);
   h->psi2 = (double *)malloc(fld);
+  h->ux = (double *)malloc(fld);
+  h->uy = (double *)malloc(fld);
+  h->K1 = (double *)malloc(fld);
+  h->K2 = (double *)malloc(fld);
+  h->Ts = (double *)malloc(fld);
   if (!h->f || !h->g || !h->f2 || !h->g2 || !h->rho || !h->jx || !h->jy || !h->E || !h->T ||
-      !h->psi || !h->psi2) {
+      !h->psi || !h->psi2 || !h->ux || !h->uy || !h->K1 || !h->K2 || !h->Ts) {
     lbmref_destroy(h);
     return -2;
   }
@@ -200,6 +222,11 @@ int lbmref_destroy(lbmref_handle h) {
   free(h->T);
   free(h->psi);
   free(h->psi2);
+  free(h->ux);
+  free(h->uy);
+  free(h->K1);
+  free(h->K2);
+  free(h->Ts);
   free(h);
   return 0;
 }
@@ -289,6 +316,8 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
       double r = h->rho[c];
       double ux = (h->jx[c] + 0.5 * Fx[c]) / r;
       double uy = (h->jy[c] + 0.5 * Fy[c]) / r;
+      h->ux[c] = ux;
+      h->uy[c] = uy;
       double cvT = p->cv * h->T[c];
       double feq[9], fi_force[9], ci[9];
       lbmref_feq(r, ux, uy, feq);
@@ -335,9 +364,75 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
   }
 }
 
+/* value of a node field at (x, y), which may lie one node beyond a wall:
+ * periodic wrap, or the mirrored boundary node; `dirichlet` gives the
+ * temperature ghost 2 T_w - T(mirrored node) instead */
+static double ghost(lbmref_handle h, const double *phi, int x, int y, int is_T) {
+  const lbmref_params *p = &h->p;
+  const int nx = p->nx, ny = p->ny;
+  int xm = x, ym = y;
+  int outx = x < 0 || x >= nx, outy = y < 0 || y >= ny;
+  if (outx) xm = p->wall_x ? (x < 0 ? 0 : nx - 1) : (x < 0 ? x + nx : x - nx);
+  if (outy) ym = p->wall_y ? (y < 0 ? 0 : ny - 1) : (y < 0 ? y + ny : y - ny);
+  double v = phi[IDX(h, xm, ym)];
+  if (!is_T) return v;
+  /* the y wall's condition applies where both are crossed (corners) */
+  if (outy && p->wall_y) {
+    int th = y < 0 ? p->thermal_bottom : p->thermal_top;
+    double Tw = y < 0 ? p->T_bottom : p->T_top;
+    return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;
+  }
+  if (outx && p->wall_x) {
+    int th = x < 0 ? p->thermal_left : p->thermal_right;
+    double Tw = x < 0 ? p->T_left : p->T_right;
+    return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;
+  }
+  return v;
+}
+
+/* K(T) of Eq. (26) at every node, with u and rho of time t */
+static void fd_rhs(lbmref_handle h, const double *T, double *K) {
+  const lbmref_params *p = &h->p;
+  const double lam_per_rho = (p->tau_g - 0.5) * p->cv * CS2;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < p->ny; ++y) {
+    for (int x = 0; x < p->nx; ++x) {
+      long c = IDX(h, x, y);
+      double gTx = 0.0, gTy = 0.0, gLx = 0.0, gLy = 0.0, lapT = 0.0;
+      for (int i = 1; i < 9; ++i) {
+        double w = w_sc(i);
+        double Tn = ghost(h, T, x + EX[i], y + EY[i], 1);
+        double rn = ghost(h, h->rho, x + EX[i], y + EY[i], 0);
+        gTx += w * Tn * EX[i];
+        gTy += w * Tn * EY[i];
+        gLx += w * lam_per_rho * rn * EX[i];
+        gLy += w * lam_per_rho * rn * EY[i];
+        lapT += 2.0 * w * (Tn - T[c]);
+      }
+      double lam = lam_per_rho * h->rho[c];
+      double div = lam * lapT + gLx * gTx + gLy * gTy;
+      K[c] = -(h->ux[c] * gTx + h->uy[c] * gTy) + div / (h->rho[c] * p->cv);
+    }
+  }
+}
+
+/* Eq. (27), read as Heun's method (dt = 1), then g = cv T f on the
+ * streamed f */
+static void fd_update(lbmref_handle h) {
+  const long n = h->n;
+  fd_rhs(h, h->T, h->K1);
+  for (long c = 0; c < n; ++c) h->Ts[c] = h->T[c] + h->K1[c];
+  fd_rhs(h, h->Ts, h->K2);
+  for (long c = 0; c < n; ++c) {
+    double Tn = h->T[c] + 0.5 * (h->K1[c] + h->K2[c]);
+    for (int i = 0; i < 9; ++i) h->g2[PL(h, i) + c] = h->p.cv * Tn * h->f2[PL(h, i) + c];
+  }
+}
+
 int lbmref_step(lbmref_handle h, int n, int treatment) {
   if (!h || n < 0) return -1;
-  if (treatment != LBMREF_PLAIN && treatment != LBMREF_CORRECTED) return -1;
+  if (treatment != LBMREF_PLAIN && treatment != LBMREF_CORRECTED && treatment != LBMREF_FD_RK2)
+    return -1;
   if (!h->have_fields) return -6;
   double *Fx = (double *)malloc((size_t)h->n * sizeof(double));
   double *Fy = (double *)malloc((size_t)h->n * sizeof(double));
@@ -352,6 +447,7 @@ int lbmref_step(lbmref_handle h, int n, int treatment) {
     h->clamp_count += clamps;
     total_force(h, Fx, Fy);
     pass_collide_stream(h, Fx, Fy, treatment);
+    if (treatment == LBMREF_FD_RK2) fd_update(h);
     double *t;
     t = h->f; h->f = h->f2; h->f2 = t;
     t = h->g; h->g = h->g2; h->g2 = t;

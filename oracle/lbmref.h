@@ -19,7 +19,7 @@
 extern "C" {
 #endif
 
-enum { LBMREF_PLAIN = 0, LBMREF_CORRECTED = 1 };
+enum { LBMREF_PLAIN = 0, LBMREF_CORRECTED = 1, LBMREF_FD_RK2 = 2 };
 enum { LBMREF_EOS_CS = 0, LBMREF_EOS_IDEAL = 1 };
 enum { LBMREF_THERMAL_DIRICHLET = 0, LBMREF_THERMAL_ADIABATIC = 1 };
 

@@ -12,6 +12,7 @@ from . import build as _build
 
 PLAIN = 0
 CORRECTED = 1
+FD_RK2 = 2
 
 _EOS = {"cs": 0, "ideal": 1}
 _THERMAL = {"dirichlet": 0, "adiabatic": 1}
