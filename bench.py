@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP64/FP32-global side runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-lattice batch section")
     ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady-state (residual) section")
+    ap.add_argument("--steady-cases", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
     return ap.parse_args()
@@ -181,6 +183,41 @@ def cpu_baseline(p, rho, T, treatment, seconds):
                       % (n, p["nx"], p["ny"], cores, el)}
 
 
+WARM_WEIGHTS = os.path.join(ROOT, "paper_1405_2232_amd", "warmstart_64.npz")
+
+
+def steady_section(count, torch, n=64, target=1e-8, cap=600000):
+    """Wall time to a one-step residual of `target` on held-out steady-state
+    cases (seeds 100000.., n x n, 1-3 droplets between Dirichlet walls, EOS
+    at T0, FP64 storage): plain = one lattice at a time from the initial
+    fields; batched = all cases in one batch; warm = batched, started from
+    the trained network's prediction (inference and screening timed in)."""
+    from paper_1405_2232_amd import inputs, warmstart
+    cases = [inputs.warmstart_case(100000 + s, n=n, max_drops=3) for s in range(count)]
+    plain = warmstart.solve_single(cases, target=target, cap=cap)
+    cold = warmstart.solve(cases, target=target, cap=cap, keep=False)
+    out = {"cases": count, "n": n, "target": target, "cap": cap, "storage": "f64",
+           "plain_s": round(plain["wall_s"], 2), "plain_converged": sum(s is not None for s in plain["steps"]),
+           "batched_cold_s": round(cold["wall_s"], 2),
+           "batched_cold_converged": sum(s is not None for s in cold["steps"])}
+    if os.path.exists(WARM_WEIGHTS):
+        t0 = time.perf_counter()
+        ws = warmstart.WarmStart(n, params=warmstart.load_params(WARM_WEIGHTS))
+        preds = ws.predict(cases)
+        inits, rp, rc = warmstart.screen(cases, preds)
+        t_inf = time.perf_counter() - t0
+        warm = warmstart.solve(cases, inits=inits, target=target, cap=cap, keep=False)
+        both = [i for i in range(count) if cold["steps"][i] is not None and warm["steps"][i] is not None]
+        out.update({
+            "warm_s": round(warm["wall_s"] + t_inf, 2), "warm_inference_s": round(t_inf, 3),
+            "warm_converged": sum(s is not None for s in warm["steps"]),
+            "warm_accepted": sum(p is not None for p in inits),
+            "steps_cold_vs_warm_on_both": [sum(cold["steps"][i] for i in both), sum(warm["steps"][i] for i in both)],
+            "speedup_warm_vs_plain": round(plain["wall_s"] / (warm["wall_s"] + t_inf), 2)})
+    out["speedup_batched_vs_plain"] = round(plain["wall_s"] / cold["wall_s"], 2)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +315,8 @@ def main():
     }
     if not args.no_batch:
         line["batched"] = batch_section(args.batch_steps, torch)
+    if not args.no_steady:
+        line["steady_state"] = steady_section(args.steady_cases, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, rho, T, treatment, args.cpu_seconds)
     print(json.dumps(line), flush=True)

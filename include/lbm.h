@@ -51,8 +51,13 @@ enum {
 
 /* temperature treatments */
 enum {
-  LBM_PLAIN = 0,    /* Eq. (7): carries the forcing-term effect of Eq. (23) */
-  LBM_CORRECTED = 1 /* Eq. (24) with C_i of Eq. (25): recovers Eq. (A11) */
+  LBM_PLAIN = 0,     /* Eq. (7): carries the forcing-term effect of Eq. (23) */
+  LBM_CORRECTED = 1, /* Eq. (24) with C_i of Eq. (25): recovers Eq. (A11) */
+  LBM_FD_RK2 = 2     /* Eq. (26) by isotropic central differences and the
+                        two-stage Runge-Kutta scheme of Eq. (27) (Heun's
+                        form), u and rho of time t in both stages; the
+                        temperature is then carried as g_i = cv T f_i.
+                        Single lattices only (lbm_batch_step rejects it). */
 };
 
 /* storage precision of the distributions */

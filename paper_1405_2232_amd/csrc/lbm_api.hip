@@ -87,6 +87,8 @@ bool compute_layout(const lbm_params *p, Layout *L) {
   off += align_up(lbmdev::kPartials * sizeof(double), kAlign);
   L->off_counters = off;
   off += align_up(8 * sizeof(unsigned long long), kAlign);
+  L->off_fd = off;  // first stage of the finite-difference treatment
+  off += align_up(n * sizeof(double), kAlign);
   L->total = off;
   return true;
 }
@@ -155,6 +157,11 @@ Model make_model(const lbm_params *p, const Layout &L) {
   m.wall_E[1] = p->cv * p->T_right;
   m.wall_E[2] = p->cv * p->T_bottom;
   m.wall_E[3] = p->cv * p->T_top;
+  m.T_wall[0] = p->T_left;
+  m.T_wall[1] = p->T_right;
+  m.T_wall[2] = p->T_bottom;
+  m.T_wall[3] = p->T_top;
+  m.lam_per_rho = (p->tau_g - 0.5) * p->cv * (1.0 / 3.0);
   if (p->precision == LBM_FP32_DEV) m.rho_ref = p->rho_ref;
   if (p->precision != LBM_FP64) m.cvT_ref = p->cv * p->T_ref;
   return m;
@@ -258,6 +265,7 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->buf[1] = h->ws + L.off_buf[1];
   h->staging = (double *)(h->ws + L.off_staging);
   h->snap = (double *)(h->ws + L.off_snap);
+  h->fd = (double *)(h->ws + L.off_fd);
   h->partials = (double *)(h->ws + L.off_partials);
   h->out = (double *)(h->ws + L.off_out);
   h->counters = (unsigned long long *)(h->ws + L.off_counters);
@@ -290,13 +298,38 @@ int lbm_init_fields(lbm_handle h, const double *rho, const double *ux, const dou
   return LBM_OK;
 }
 
+namespace {
+bool treatment_ok(int t) { return t == LBM_PLAIN || t == LBM_CORRECTED || t == LBM_FD_RK2; }
+
+// one time step; the finite-difference treatment takes the moments of time
+// t first, runs the LB step for f (its g result is overwritten) and then
+// the two finite-difference stages, which leave g = cv T f
+hipError_t one_step(lbm_ctx *h, int treatment) {
+  if (treatment == LBM_FD_RK2) {
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    lbmdev::MomentsOut mo{};
+    mo.rho = h->staging;
+    mo.ux = h->staging + n;
+    mo.uy = h->staging + 2 * n;
+    mo.T = h->staging + 3 * n;
+    hipError_t e = lbmdev::launch_moments(h->m, h->tm, h->st, h->buf[h->cur], mo, h->stream);
+    if (e != hipSuccess) return e;
+    e = lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], LBM_PLAIN,
+                            h->counters, h->stream);
+    if (e != hipSuccess) return e;
+    return lbmdev::launch_fd(h->m, h->st, h->staging, h->fd, h->buf[1 - h->cur], h->stream);
+  }
+  return lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
+                             h->counters, h->stream);
+}
+}  // namespace
+
 int lbm_step(lbm_handle h, int n, int treatment) {
   if (!h || n < 1) return LBM_EINVAL;
-  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  if (!treatment_ok(treatment)) return LBM_EINVAL;
   if (!h->initialized) return LBM_ESTATE;
   for (int k = 0; k < n; ++k) {
-    HIPCHK(lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur],
-                               treatment, h->counters, h->stream));
+    HIPCHK(one_step(h, treatment));
     h->cur ^= 1;
     h->steps += 1;
     if (h->check_every > 0 && h->steps % h->check_every == 0) {
@@ -367,12 +400,11 @@ int lbm_totals(lbm_handle h, double out[8]) {
 
 int lbm_step_residual(lbm_handle h, int treatment, double *residual) {
   if (!h || !residual) return LBM_EINVAL;
-  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  if (!treatment_ok(treatment)) return LBM_EINVAL;
   if (!h->initialized) return LBM_ESTATE;
   int rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 1, 0);
   if (rc) return rc;
-  HIPCHK(lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
-                             h->counters, h->stream));
+  HIPCHK(one_step(h, treatment));
   h->cur ^= 1;
   h->steps += 1;
   rc = run_moments(h, nullptr, nullptr, nullptr, nullptr, 0, 1);

@@ -28,6 +28,7 @@ struct Layout {
   int max_blocks;
   size_t off_out;         // kPartials doubles
   size_t off_counters;    // 8 u64
+  size_t off_fd;          // 1 dense FP64 plane (finite-difference stage)
   size_t total;
 };
 
@@ -52,7 +53,7 @@ struct lbm_ctx {
   char *ws;
   void *buf[2];
   int cur;
-  double *staging, *snap, *partials, *out;
+  double *staging, *snap, *partials, *out, *fd;
   unsigned long long *counters;
   long long steps;
   int initialized;

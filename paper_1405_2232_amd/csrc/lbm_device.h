@@ -36,6 +36,8 @@ struct Model {
   double wall_E[4];          // cv * T_w per wall (multiplied by the node's rho)
   double rho_ref;            // ST_F32_GLOBAL density shift
   double cvT_ref;            // cv * T_ref: energy shift per unit reference density
+  double lam_per_rho;        // (tau_g - 1/2) cv c_s^2: conductivity over density
+  double T_wall[4];          // wall temperatures (finite-difference treatment)
 };
 
 // What one launch of the tile kernel does.
@@ -80,6 +82,11 @@ hipError_t launch_plane_to_f64(const Model &m, int st, const void *src, int q, d
 hipError_t launch_plane_from_f64(const Model &m, int st, void *dst, int q, const double *in,
                                  hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Finite-difference temperature update (Eqs. (26)-(27)): from the moments of
+// time t (dense planes mom[0..3] = rho, ux, uy, T, each nx*ny) and the
+// streamed distributions in dst, writes g = cv T^(t+1) f into dst; k1 is a
+// dense scratch plane.
+hipError_t launch_fd(const Model &m, int st, const double *mom, double *k1, void *dst, hipStream_t s);
 
 // Byte offset of the FP16 reference plane inside one distribution buffer.
 __host__ __device__ inline size_t ref_plane_offset(const Model &m, int st) {

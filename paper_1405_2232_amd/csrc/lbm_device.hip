@@ -411,28 +411,36 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
   };
 
   if (PF >= 2 && MODE == MODE_STEP) {
-    // three row buffers in rotating roles, unrolled so that no loaded
-    // register is copied (a copy would wait for the load in flight)
-    Row<S> R0, R1, R2;
-    Mom<C> M0, M1, M2;
-    load_row(-1, R2);
-    load_row(0, R0);
-    load_row(1, R1);
-    psi_row(-1, R2, M2, false);
-    psi_row(0, R0, M0, true);
-    auto iter = [&](int k, const Row<S> &cur, const Mom<C> &mc, const Row<S> &nxt, Mom<C> &mn,
-                    Row<S> &pre) {
-      // unconditional look-ahead: past the band it re-reads the band's last
-      // (halo) row, which the previous iteration left in cache
-      load_row(min(k + 2, n), pre);
-      psi_row(k + 1, nxt, mn, k + 1 < n);
-      __syncthreads();
-      collide_row(k, cur, mc);
-    };
-    for (int k = 0; k < n; k += 3) {
-      iter(k, R0, M0, R1, M1, R2);
-      if (k + 1 < n) iter(k + 1, R1, M1, R2, M2, R0);
-      if (k + 2 < n) iter(k + 2, R2, M2, R0, M0, R1);
+    // PF + 1 row buffers in rotating roles: at row k the buffers hold rows
+    // k (collide), k + 1 (psi) and k + 2 .. k + PF (loads in flight).  The
+    // loop is unrolled over a full rotation so that every buffer index is a
+    // constant and no loaded register is ever copied (a copy would wait for
+    // the load in flight).
+    // the moments of a row are kept from its psi evaluation to its
+    // collision in two alternating slots; the unrolled span covers whole
+    // rotations of both
+    constexpr int NB = PF + 1;
+    constexpr int SPAN = (NB % 2) ? 2 * NB : NB;
+    Row<S> R[NB];
+    Mom<C> M[2];
+    load_row(-1, R[NB - 1]);
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_row(j, R[j]);
+    psi_row(-1, R[NB - 1], M[1], false);
+    psi_row(0, R[0], M[0], true);
+    for (int k = 0; k < n; k += SPAN) {
+#pragma unroll
+      for (int j = 0; j < SPAN; ++j) {
+        const int kk = k + j;
+        if (kk < n) {
+          // unconditional look-ahead: past the band it re-reads the band's
+          // last (halo) row, which an earlier iteration left in cache
+          load_row(min(kk + PF, n), R[(j + PF) % NB]);
+          psi_row(kk + 1, R[(j + 1) % NB], M[(j + 1) & 1], kk + 1 < n);
+          __syncthreads();
+          collide_row(kk, R[j % NB], M[j & 1]);
+        }
+      }
     }
   } else {
     Row<S> R0, R1;
@@ -616,6 +624,100 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
   }
 }
 
+// ---------------------------------------------------------------------------
+// Finite-difference temperature treatment, Eq. (26):
+//   K(T) = -u . grad T + div(lambda grad T) / (rho cv),
+//   lambda = (tau_g - 1/2) cv rho c_s^2,
+// with the isotropic central differences grad phi = sum_i w_i phi(x+e_i) e_i
+// and lap phi = 2 sum_i w_i (phi(x+e_i) - phi(x)) (w = 1/3 on the axes, 1/12
+// on the diagonals) and div(lambda grad T) = lambda lap T + grad lambda .
+// grad T; two stages per step, Eq. (27) taken as Heun's method:
+//   k1 = K(T^t), T^(t+1) = T^t + (k1 + K(T^t + k1)) / 2,
+// with rho and u of time t in both stages.
+
+// a field one node beyond the lattice at most: periodic wrap or the
+// mirrored boundary node
+__device__ inline long long fd_node(const Model &m, int x, int y, bool &ox, bool &oy) {
+  ox = x < 0 || x >= m.nx;
+  oy = y < 0 || y >= m.ny;
+  if (ox) x = m.wall_x ? (x < 0 ? 0 : m.nx - 1) : (x < 0 ? x + m.nx : x - m.nx);
+  if (oy) y = m.wall_y ? (y < 0 ? 0 : m.ny - 1) : (y < 0 ? y + m.ny : y - m.ny);
+  return (long long)y * m.nx + x;
+}
+
+// temperature ghost beyond a wall (halfway): 2 T_w - T(mirror) for a
+// Dirichlet wall, T(mirror) for an adiabatic one; the y wall rules corners
+__device__ inline double fd_T_ghost(const Model &m, double v, int x, int y, bool ox, bool oy) {
+  if (oy && m.wall_y) {
+    const int k = y < 0 ? 2 : 3;
+    return m.thermal[k] == 0 ? 2.0 * m.T_wall[k] - v : v;
+  }
+  if (ox && m.wall_x) {
+    const int k = x < 0 ? 0 : 1;
+    return m.thermal[k] == 0 ? 2.0 * m.T_wall[k] - v : v;
+  }
+  return v;
+}
+
+// K at node (x, y); Tval(c) gives the stage temperature at an in-lattice node
+template <typename TV>
+__device__ inline double fd_K(const Model &m, const double *rho, double ux, double uy, int x, int y,
+                              long long c, TV Tval) {
+  constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double Tc = Tval(c);
+  double gTx = 0.0, gTy = 0.0, gLx = 0.0, gLy = 0.0, lap = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+    const int xn = x + ex[i], yn = y + ey[i];
+    bool ox, oy;
+    const long long cn = fd_node(m, xn, yn, ox, oy);
+    const double Tn = fd_T_ghost(m, Tval(cn), xn, yn, ox, oy);
+    const double ln = m.lam_per_rho * rho[cn];
+    gTx += w * Tn * ex[i];
+    gTy += w * Tn * ey[i];
+    gLx += w * ln * ex[i];
+    gLy += w * ln * ey[i];
+    lap += 2.0 * w * (Tn - Tc);
+  }
+  const double div = m.lam_per_rho * rho[c] * lap + gLx * gTx + gLy * gTy;
+  return -(ux * gTx + uy * gTy) + div / (rho[c] * m.cv);
+}
+
+__global__ void k_fd1(Model m, const double *__restrict__ mom, double *__restrict__ k1) {
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  const double *rho = mom, *ux = mom + n, *uy = mom + 2 * n, *T = mom + 3 * n;
+  k1[c] = fd_K(m, rho, ux[c], uy[c], x, y, c, [&](long long q) { return T[q]; });
+}
+
+template <int ST>
+__global__ void k_fd2(Model m, const double *__restrict__ mom, const double *__restrict__ k1,
+                      void *__restrict__ dst_v) {
+  using S = typename Prec<ST>::S;
+  const long long n = (long long)m.nx * m.ny;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int x = (int)(c % m.nx), y = (int)(c / m.nx);
+  const double *rho = mom, *ux = mom + n, *uy = mom + 2 * n, *T = mom + 3 * n;
+  const double k2 = fd_K(m, rho, ux[c], uy[c], x, y, c, [&](long long q) { return T[q] + k1[q]; });
+  const double Tn = T[c] + 0.5 * (k1[c] + k2);
+  S *dst = (S *)dst_v;
+  const _Float16 *ref = (const _Float16 *)((const char *)dst_v + ref_plane_offset(m, ST));
+  const long long idx = (long long)y * m.pitch + x;
+  const double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  const double cvT = m.cv * Tn;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double w = wgt<double>(i);
+    const double f = (double)dst[i * m.plane + idx] + w * rf;
+    dst[(9 + i) * m.plane + idx] = (S)(cvT * f - w * rf * m.cvT_ref);
+  }
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // plain streaming copy: each lane moves four 16-byte words per trip
@@ -679,13 +781,27 @@ static hipError_t launch_tile_st(const Model &m, const Tiling &t, int st, const 
 hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *cc, hipStream_t s) {
   MomentsOut mo{};
-  if (t.pf >= 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
+  if (t.pf >= 3) return launch_tile_st<MODE_STEP, 3>(m, t, st, src, dst, treatment, cc, mo, s);
+  if (t.pf == 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
   return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);
 }
 
 hipError_t launch_moments(const Model &m, const Tiling &t, int st, const void *src,
                           const MomentsOut &o, hipStream_t s) {
   return launch_tile_st<MODE_MOMENTS, 1>(m, t, st, src, nullptr, 0, nullptr, o, s);
+}
+
+hipError_t launch_fd(const Model &m, int st, const double *mom, double *k1, void *dst, hipStream_t s) {
+  const long long n = (long long)m.nx * m.ny;
+  const dim3 g(grid1d(n, 256)), b(256);
+  hipLaunchKernelGGL(k_fd1, g, b, 0, s, m, mom, k1);
+  switch (st) {
+    case ST_F64: hipLaunchKernelGGL(k_fd2<ST_F64>, g, b, 0, s, m, mom, k1, dst); break;
+    case ST_F32_GLOBAL: hipLaunchKernelGGL(k_fd2<ST_F32_GLOBAL>, g, b, 0, s, m, mom, k1, dst); break;
+    case ST_F32_LOCAL: hipLaunchKernelGGL(k_fd2<ST_F32_LOCAL>, g, b, 0, s, m, mom, k1, dst); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const Model &m, int st, void *dst, const double *rho, const double *ux,
@@ -759,15 +875,22 @@ hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char 
     else if (bx == 256) LBM_B(ST_, 256, PF_); \
     else return hipErrorInvalidValue;         \
   } while (0)
+#define LBM_PF(ST_)                      \
+  do {                                   \
+    if (pf >= 3) LBM_BX(ST_, 3);         \
+    else if (pf == 2) LBM_BX(ST_, 2);    \
+    else LBM_BX(ST_, 1);                 \
+  } while (0)
   if (st == ST_F64) {
-    if (pf >= 2) LBM_BX(ST_F64, 2); else LBM_BX(ST_F64, 1);
+    LBM_PF(ST_F64);
   } else if (st == ST_F32_GLOBAL) {
-    if (pf >= 2) LBM_BX(ST_F32_GLOBAL, 2); else LBM_BX(ST_F32_GLOBAL, 1);
+    LBM_PF(ST_F32_GLOBAL);
   } else if (st == ST_F32_LOCAL) {
-    if (pf >= 2) LBM_BX(ST_F32_LOCAL, 2); else LBM_BX(ST_F32_LOCAL, 1);
+    LBM_PF(ST_F32_LOCAL);
   } else {
     return hipErrorInvalidValue;
   }
+#undef LBM_PF
 #undef LBM_BX
 #undef LBM_B
   return hipGetLastError();

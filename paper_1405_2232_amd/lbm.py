@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDOMAIN, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PLAIN, CORRECTED = 0, 1
+PLAIN, CORRECTED, FD_RK2 = 0, 1, 2
 FP64, FP32_DEV, FP32_LOCAL = 0, 1, 2
 _EOS = {"cs": 0, "ideal": 1}
 _THERMAL = {"dirichlet": 0, "adiabatic": 1}

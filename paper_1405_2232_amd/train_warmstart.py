@@ -1,6 +1,9 @@
 """Train the warm-start network on solver trajectories and evaluate it.
 
-    python -m paper_1405_2232_amd.train_warmstart --train 512 --test 64 --out DIR
+    python -m paper_1405_2232_amd.train_warmstart --out DIR
+
+(defaults: 64 x 64 cases with 1-3 droplets, 1024 training solves to a
+1e-7 residual, 120 epochs, 64 held-out cases evaluated at 1e-8)
 
 Steps (all on the GPU):
   1. solve the training cases (seeds 0..train-1) to the residual target in
@@ -10,8 +13,8 @@ Steps (all on the GPU):
      screened by its one-step residual, cold start where rejected), and
      report steps and wall time to the target for both, the warm time
      including the network's inference.
-Writes DIR/warmstart_weights.npz (the trained parameters) and
-DIR/warmstart_eval.json.
+Writes DIR/warmstart_<n>.npz (the trained parameters; the benchmark loads
+paper_1405_2232_amd/warmstart_64.npz) and DIR/warmstart_eval.json.
 """
 import argparse
 import json
@@ -28,14 +31,17 @@ def log(*a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--train", type=int, default=1024)
     ap.add_argument("--test", type=int, default=64)
-    ap.add_argument("--batch-solve", type=int, default=128)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch-solve", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--target", type=float, default=1e-8)
-    ap.add_argument("--cap", type=int, default=200000)
+    ap.add_argument("--target", type=float, default=1e-8, help="residual target of the evaluation")
+    ap.add_argument("--train-target", type=float, default=1e-7, help="residual target of the training solves")
+    ap.add_argument("--cap", type=int, default=600000)
+    ap.add_argument("--train-cap", type=int, default=400000)
+    ap.add_argument("--max-drops", type=int, default=3)
     ap.add_argument("--out", default="gpurun_out")
     args = ap.parse_args(argv)
 
@@ -44,15 +50,15 @@ def main(argv=None):
 
     os.makedirs(args.out, exist_ok=True)
     t_all = time.perf_counter()
-    train_cases = [inputs.warmstart_case(s, n=args.n) for s in range(args.train)]
-    test_cases = [inputs.warmstart_case(100000 + s, n=args.n) for s in range(args.test)]
+    train_cases = [inputs.warmstart_case(s, n=args.n, max_drops=args.max_drops) for s in range(args.train)]
+    test_cases = [inputs.warmstart_case(100000 + s, n=args.n, max_drops=args.max_drops) for s in range(args.test)]
 
     # 1. training trajectories
     steady, keep = [], []
     t0 = time.perf_counter()
     for k in range(0, len(train_cases), args.batch_solve):
         part = train_cases[k:k + args.batch_solve]
-        r = solve(part, target=args.target, cap=args.cap)
+        r = solve(part, target=args.train_target, cap=args.train_cap)
         for i, st in enumerate(r["steps"]):
             if st is not None:
                 keep.append(k + i)
@@ -68,22 +74,29 @@ def main(argv=None):
     hist = ws.train(data, epochs=args.epochs, lr=args.lr, log=log)
     train_s = time.perf_counter() - t0
     del data
-    np.savez(os.path.join(args.out, "warmstart_weights.npz"), **{
+    np.savez(os.path.join(args.out, "warmstart_%d.npz" % args.n), **{
         k: v.astype(np.float32) for k, v in ws.net.get_params().items()})
 
     # 3. held-out evaluation: cold, then warm (inference timed in)
     cold = solve(test_cases, target=args.target, cap=args.cap, keep=False)
     t0 = time.perf_counter()
     preds = ws.predict(test_cases)
-    inits = screen(test_cases, preds)
+    inits, rp, rc = screen(test_cases, preds)
     infer_s = time.perf_counter() - t0
     warm = solve(test_cases, inits=inits, target=args.target, cap=args.cap, keep=False)
+    raw = solve(test_cases, inits=preds, target=args.target, cap=args.cap, keep=False)
+    log("predicted residuals", ["%.1e" % r for r in rp])
+    log("cold residuals", ["%.1e" % r for r in rc])
+    log("cold steps", cold["steps"])
+    log("warm steps", warm["steps"])
+    log("unscreened warm steps", raw["steps"])
     both = [i for i in range(len(test_cases)) if cold["steps"][i] is not None and warm["steps"][i] is not None]
     cs = np.array([cold["steps"][i] for i in both], dtype=float)
     wsteps = np.array([warm["steps"][i] for i in both], dtype=float)
     res = {
         "n": args.n, "train_cases": args.train, "train_converged": len(keep), "test_cases": args.test,
-        "target": args.target, "cap": args.cap, "epochs": args.epochs, "loss": hist,
+        "target": args.target, "cap": args.cap, "train_target": args.train_target, "train_cap": args.train_cap,
+        "max_drops": args.max_drops, "epochs": args.epochs, "loss": hist,
         "data_generation_s": round(gen_s, 1), "training_s": round(train_s, 1),
         "accepted_predictions": int(sum(p is not None for p in inits)),
         "cold": {"converged": int(sum(s is not None for s in cold["steps"])), "wall_s": round(cold["wall_s"], 2),
@@ -92,6 +105,10 @@ def main(argv=None):
                  "wall_s": round(warm["wall_s"] + infer_s, 2), "inference_and_screen_s": round(infer_s, 2),
                  "mean_steps": float(wsteps.mean()) if len(wsteps) else None},
         "step_ratio_warm_over_cold": float(wsteps.sum() / cs.sum()) if len(cs) else None,
+        "unscreened": {"converged": int(sum(s is not None for s in raw["steps"])),
+                       "steps": raw["steps"]},
+        "cold_steps": cold["steps"], "warm_steps": warm["steps"],
+        "predicted_residual": rp, "cold_residual": rc,
         "total_s": round(time.perf_counter() - t_all, 1),
     }
     with open(os.path.join(args.out, "warmstart_eval.json"), "w") as fp:

@@ -80,15 +80,48 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
     return out
 
 
+def solve_single(cases, precision="fp64", target=1e-8, cap=200000, chunk=1000, treatment=CORRECTED):
+    """The plain way: one lattice at a time (single-lattice launches), cold
+    start, residual checked every `chunk` steps.  Returns per-case steps and
+    the wall time."""
+    import torch
+    from .lbm import Lattice
+    t0 = time.perf_counter()
+    steps = []
+    for p, rho, T in cases:
+        g = Lattice(p, precision)
+        g.init_fields(rho, T)
+        done, st = 0, None
+        while done < cap:
+            g.step(chunk - 1, treatment)
+            done += chunk
+            try:
+                r = g.step_residual(treatment)
+            except RuntimeError:
+                break
+            if r < target:
+                st = done
+                break
+        steps.append(st)
+        g.close()
+    torch.cuda.synchronize()
+    return {"steps": steps, "wall_s": time.perf_counter() - t0, "cap": cap}
+
+
+def load_params(path):
+    with np.load(path) as z:
+        return {k: z[k].astype(np.float64) for k in z.files}
+
+
 class WarmStart:
     """The network plus its training and inference on n x n cases."""
 
-    def __init__(self, n, batch=8, Tc=None, seed=0):
+    def __init__(self, n, batch=8, Tc=None, seed=0, params=None):
         from . import inputs
         from .nn import init_params
         self.n, self.B = n, batch
         self.Tc = Tc if Tc is not None else inputs.cs_tc()
-        self.net = UNet(batch, n, n, wrap_x=True, params=init_params(seed))
+        self.net = UNet(batch, n, n, wrap_x=True, params=params if params is not None else init_params(seed))
 
     def _upload(self, arrays):
         import torch
@@ -149,8 +182,11 @@ class WarmStart:
                 log("epoch %d loss %.3e" % (ep, hist[-1]))
         return hist
 
-    def predict(self, cases):
-        """Predicted steady (rho, T) FP64 host arrays for each case."""
+    def predict(self, cases, conserve_mass=True):
+        """Predicted steady (rho, T) FP64 host arrays for each case.  The LB
+        step conserves mass, so the predicted density is rescaled to the
+        initial field's total mass (a warm start must not change which
+        steady state the solve reaches)."""
         import torch
         out = []
         N = len(cases)
@@ -167,23 +203,38 @@ class WarmStart:
             self.net.unpack(r1, t1, self.Tc)
             r1, t1 = r1.cpu().numpy(), t1.cpu().numpy()
             for j in range(len(chunk)):
-                out.append((r1[j], t1[j]))
+                rj = r1[j]
+                if conserve_mass:
+                    rj = rj * (float(chunk[j][1].sum()) / float(rj.sum()))
+                out.append((rj, t1[j]))
         return out
 
 
-def screen(cases, preds, precision="fp64", reject=1e-3, treatment=CORRECTED):
-    """One-step residual of each prediction used as an initial state;
-    predictions above `reject` (or non-finite) are replaced by None (the
-    cold start)."""
+def residuals(cases, fields, precision="fp64", treatment=CORRECTED):
+    """One-step residual of each (rho, T) used as an initial state (inf
+    where the step fails)."""
     refs = [(float(r.mean()), float(t.mean())) for _, r, t in cases]
     b = Batch([c[0] for c in cases], precision, refs=refs)
-    keep = []
-    for i, (m, pr) in enumerate(zip(b.members, preds)):
+    out = []
+    for m, fr in zip(b.members, fields):
         try:
-            m.init_fields(*pr)
+            m.init_fields(*fr)
             r = m.step_residual(treatment)
         except RuntimeError:
             r = np.inf
-        keep.append(pr if (np.isfinite(r) and r <= reject) else None)
+        out.append(r if np.isfinite(r) else np.inf)
     b.close()
-    return keep
+    return out
+
+
+def screen(cases, preds, precision="fp64", reject=1e-3, factor=3.0, treatment=CORRECTED):
+    """Keep a prediction as the initial state when its one-step residual is
+    at most `reject` or at most `factor` times the cold start's own initial
+    residual (a cold start of these two-phase states already has a one-step
+    residual of about 3e-2, so an absolute 1e-3 alone would reject every
+    start); otherwise, or when non-finite, None (the cold start).  Returns
+    (kept, predicted residuals, cold residuals)."""
+    rp = residuals(cases, preds, precision, treatment)
+    rc = residuals(cases, [(c[1], c[2]) for c in cases], precision, treatment)
+    keep = [pr if (r <= reject or r <= factor * c) else None for pr, r, c in zip(preds, rp, rc)]
+    return keep, rp, rc

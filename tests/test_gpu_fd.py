@@ -1,0 +1,73 @@
+"""GPU parity of the finite-difference temperature treatment (Eqs. (26)-(27))
+against the oracle: the static droplet (EOS at the local T) in FP64 and
+FP32 per-node-reference storage, a ragged walled lattice with gravity and
+both wall conditions, the single-phase ideal-EOS cavity of Sec. III.B, and
+switching treatments mid-run."""
+import numpy as np
+import pytest
+
+from gpu_util import compare_fp32dev, compare_fp64, gpu_run, need_gpu, oracle_run, say
+from oracle import CORRECTED, FD_RK2, Oracle
+from paper_1405_2232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+def test_droplet_fd_parity(precision):
+    p, rho, T = inputs.static_droplet()
+    say("case fd droplet", precision)
+    g = gpu_run(p, rho, T, 2000, FD_RK2, precision=precision)
+    o = oracle_run(p, rho, T, 2000, FD_RK2)
+    if precision == "fp64":
+        compare_fp64(g.moments(), o.moments(), what=("fd droplet",))
+    else:
+        compare_fp32dev(g.moments(), o.moments(), what=("fd droplet fp32local",))
+
+
+def test_ragged_walls_gravity_fd_parity():
+    Tc = inputs.cs_tc()
+    p, rho, T = inputs.static_droplet(nx=77, ny=45, radius=12, seed=5)
+    p.update(wall_x=True, wall_y=True, gy=-2e-5, thermal_left="adiabatic", thermal_right="dirichlet",
+             thermal_bottom="dirichlet", thermal_top="adiabatic", T_right=0.88 * Tc,
+             T_bottom=0.83 * Tc, eos_fixed_T=True)
+    say("case fd ragged walls")
+    g = gpu_run(p, rho, T, 500, FD_RK2)
+    o = oracle_run(p, rho, T, 500, FD_RK2)
+    compare_fp64(g.moments(), o.moments(), what=("fd ragged",))
+
+
+def test_cavity_fd_parity():
+    n = 40
+    Th, Tl, mu, Pr, Ra = 1.03, 0.97, 0.1, 0.71, 1e3
+    p = dict(nx=n, ny=n, tau_f=0.5 + 3 * mu, tau_g=0.5 + 3 * mu / Pr, G=1.0, beta=0.0, eos="ideal",
+             R=1.0 / 3.0, cv=1.0, gx=0.0, gy=-Ra * mu ** 2 / ((Th - Tl) * n ** 3 * Pr), wall_x=True,
+             wall_y=True, thermal_left="dirichlet", thermal_right="dirichlet", thermal_bottom="adiabatic",
+             thermal_top="adiabatic", T_left=Th, T_right=Tl, eos_fixed_T=False, T_eos=1.0)
+    one = np.ones((n, n))
+    say("case fd cavity")
+    g = gpu_run(p, one, one, 3000, FD_RK2)
+    o = oracle_run(p, one, one, 3000, FD_RK2)
+    compare_fp64(g.moments(), o.moments(), what=("fd cavity",))
+
+
+def test_switching_treatments_mid_run():
+    from paper_1405_2232_amd.lbm import Lattice
+    p, rho, T = inputs.static_droplet(nx=48, ny=40, radius=10, seed=6)
+    g = Lattice(p, "fp64")
+    g.init_fields(rho, T)
+    o = Oracle(p)
+    o.init_fields(rho, T)
+    for tr, k in ((CORRECTED, 100), (FD_RK2, 150), (CORRECTED, 80), (FD_RK2, 20)):
+        g.step(k, tr)
+        assert o.step(k, tr) == 0
+    compare_fp64(g.moments(), o.moments(), what=("switching",))
+    # the state itself: g = cv T f after a finite-difference step
+    st = g.get_state()
+    f, gg = o.get_state()
+    assert np.abs(st[:9] - f).max() < 1e-12 and np.abs(st[9:] - gg).max() < 1e-12

@@ -138,3 +138,34 @@ def test_many_droplets_4096_windows(precision):
             worst[(x0, y0)] = (rr, ta)
             assert rr <= FP32_RHO_REL and ta <= FP32_T_ABS, ((x0, y0), rr, ta)
     say("droplets 4096 window errors", precision, worst)
+
+
+def test_many_droplets_4096_fp32_against_fp64_checkpoints():
+    """The 4096^2 droplet lattice stepped in FP32 per-node-reference storage
+    beside an FP64 run: fields compared after 2000 steps (the stated FP32
+    tolerances) and then every 5000 steps up to 20,000 (the slow drift of
+    the interfaces, recorded and bounded)."""
+    import torch
+    from paper_1405_2232_amd.lbm import Lattice
+    p, rho, T = inputs.many_droplets_gravity()
+    n = p["nx"]
+    a = Lattice(p, "fp64")
+    b = Lattice(p, "fp32local")
+    a.init_fields(rho, T)
+    b.init_fields(rho, T)
+    fa = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(4)]
+    fb = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(4)]
+    done = 0
+    for k, upto in enumerate((2000, 5000, 10000, 15000, 20000)):
+        a.step(upto - done, CORRECTED)
+        b.step(upto - done, CORRECTED)
+        done = upto
+        a.moments_device(*fa)
+        b.moments_device(*fb)
+        torch.cuda.synchronize()
+        assert a.sync() == 0 and b.sync() == 0
+        rr = float(((fb[0] - fa[0]).abs() / fa[0]).max())
+        ta = float((fb[3] - fa[3]).abs().max())
+        say("droplets 4096 fp32local vs fp64 at", upto, "rho rel", rr, "T abs", ta)
+        assert ta <= FP32_T_ABS
+        assert rr <= (FP32_RHO_REL if k == 0 else FP32_LONG_RHO_REL)
