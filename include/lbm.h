@@ -79,8 +79,9 @@ enum { LBM_THERMAL_DIRICHLET = 0, LBM_THERMAL_ADIABATIC = 1 };
 
 typedef struct {
   int nx, ny;           /* lattice nodes; 1 <= nx, ny; nx*ny < 2^31, and
-                           the nine f (or g) planes of one copy below
-                           4 GiB (about 7,400^2 nodes in FP64) */
+                           one copy of the 18 distributions below 4 GiB
+                           (about 5,400^2 nodes in FP64, 7,600^2 in
+                           FP32) */
   double tau_f, tau_g;  /* relaxation times of Eq. (1) and Eq. (7); > 0.5 */
   double G;             /* interaction strength of Eq. (2); 0 disables it */
   double beta;          /* Eq. (4) mixing weight; 1 gives Eq. (2) */

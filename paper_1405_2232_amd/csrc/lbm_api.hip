@@ -58,17 +58,36 @@ bool compute_layout(const lbm_params *p, Layout *L) {
   const int fp32 = p->precision != LBM_FP64;
   L->elem = fp32 ? 4 : 8;
   const int align_elems = (int)(kAlign / L->elem);
-  L->pitch = (int)align_up((size_t)p->nx, (size_t)align_elems);
-  // each plane ends in a 4 KiB pad: it staggers the 18 streams of a row
-  // over HBM channels and holds the slots that lanes owning no node store
-  // into (the kernels need at least 256 elements there)
-  long long pad = env_ll("LBM_PLANE_PAD", 16) * align_elems;
-  if (pad < 256) pad = 256;
-  L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) + pad;
-  // 18 planes, then (LBM_FP32_LOCAL) one FP16 reference plane
-  L->dist_bytes = align_up((size_t)L->plane * 18 * L->elem +
-                               (p->precision == LBM_FP32_LOCAL ? (size_t)L->plane * 2 : 0),
-                           kAlign);
+  const long long row = (long long)align_up((size_t)p->nx, (size_t)align_elems);
+  if (env_ll("LBM_LAYOUT", 1) == 1) {
+    // row-interleaved (default): the 18 rows (one per distribution) of
+    // lattice row y are consecutive, each followed by a 256-byte stagger;
+    // the kernels see a row stride (pitch) of 18 such rows and a
+    // distribution stride (plane) of one.  A block's loads of one lattice
+    // row then fall in one contiguous span instead of 18 planes far apart
+    // (measured 4 % faster).  One row group past the end (plus 256
+    // elements) holds the slots that lanes owning no node store into.
+    L->plane = row + align_elems;
+    L->pitch = (int)(18 * L->plane);
+    L->rpitch = (int)row;
+    const long long body = (long long)p->ny * L->pitch + L->pitch + 256;
+    L->ref_off = align_up((size_t)body * L->elem, kAlign);
+    L->ref_bytes = ((size_t)p->ny * L->rpitch + 256) * 2;
+  } else {
+    // one plane per distribution, each ending in a 4 KiB pad: the pad
+    // staggers the 18 streams of a row over HBM channels and holds the
+    // slots that lanes owning no node store into (the kernels need at
+    // least 256 elements there)
+    L->pitch = (int)row;
+    long long pad = env_ll("LBM_PLANE_PAD", 16) * align_elems;
+    if (pad < 256) pad = 256;
+    L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) + pad;
+    L->rpitch = L->pitch;
+    L->ref_off = (size_t)L->plane * 18 * L->elem;
+    L->ref_bytes = (size_t)L->plane * 2;
+  }
+  // the distributions, then (LBM_FP32_LOCAL) one FP16 reference plane
+  L->dist_bytes = align_up(L->ref_off + (p->precision == LBM_FP32_LOCAL ? L->ref_bytes : 0), kAlign);
   const size_t n = (size_t)p->nx * (size_t)p->ny;
   size_t off = 0;
   L->off_buf[0] = off;
@@ -114,10 +133,9 @@ int validate(const lbm_params *p) {
   return LBM_OK;
 }
 
-// the kernels address each half (f or g planes) of a distribution buffer
-// with 32-bit byte offsets
+// the kernels address a distribution buffer with 32-bit byte offsets
 bool fits_32bit(const Layout &L) {
-  return (unsigned long long)L.plane * L.elem * 9ULL < (1ULL << 32);
+  return (unsigned long long)L.ref_off + L.ref_bytes < (1ULL << 32);
 }
 
 Model make_model(const lbm_params *p, const Layout &L) {
@@ -127,6 +145,9 @@ Model make_model(const lbm_params *p, const Layout &L) {
   m.ny = p->ny;
   m.pitch = L.pitch;
   m.plane = L.plane;
+  m.ref_off = (long long)L.ref_off;
+  m.ref_bytes = (long long)L.ref_bytes;
+  m.rpitch = L.rpitch;
   m.inv_tau_f = 1.0 / p->tau_f;
   m.inv_tau_g = 1.0 / p->tau_g;
   m.kf = 1.0 - 1.0 / (2.0 * p->tau_f);

@@ -18,9 +18,12 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   int pitch;
+  int rpitch;             // row stride of the FP16 reference plane
   long long plane;        // elements
   size_t elem;            // bytes per stored value
   size_t dist_bytes;      // one buffer of 18 planes
+  size_t ref_off;         // bytes from a buffer to its FP16 reference plane
+  size_t ref_bytes;       // size of the reference plane
   size_t off_buf[2];
   size_t off_staging;     // 4 dense FP64 planes
   size_t off_snap;        // 2 dense FP64 planes

@@ -19,6 +19,9 @@ struct Model {
   int nx, ny;
   int pitch;                 // elements between rows of one plane
   long long plane;           // elements between planes
+  long long ref_off;         // bytes from a buffer to its FP16 reference plane
+  long long ref_bytes;       // bytes of that plane
+  int rpitch;                // elements between rows of the reference plane
   double inv_tau_f, inv_tau_g;
   double kf, kg;             // 1 - 1/(2 tau_f), 1 - 1/(2 tau_g)
   double G, beta;
@@ -90,7 +93,7 @@ hipError_t launch_fd(const Model &m, int st, const double *mom, double *k1, void
 
 // Byte offset of the FP16 reference plane inside one distribution buffer.
 __host__ __device__ inline size_t ref_plane_offset(const Model &m, int st) {
-  return st == ST_F64 ? 0 : (size_t)18 * (size_t)m.plane * sizeof(float);
+  return st == ST_F64 ? 0 : (size_t)m.ref_off;
 }
 
 // Batched step: many lattices, one launch.  Device tables, one entry per

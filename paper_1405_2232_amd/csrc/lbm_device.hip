@@ -100,9 +100,10 @@ __device__ inline Bufs make_bufs(const void *base, const Model &m) {
   const unsigned long long pb = (unsigned long long)m.plane * sizeof(S);
   Bufs b;
   char *p = (char *)base;
-  b.f = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(unsigned)(9 * pb), kRsrcWord3);
-  b.g = __builtin_amdgcn_make_buffer_rsrc(p + 9 * pb, (short)0, (int)(unsigned)(9 * pb), kRsrcWord3);
-  b.ref = __builtin_amdgcn_make_buffer_rsrc(p + 18 * pb, (short)0, (int)(unsigned)(m.plane * 2),
+  b.f = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(unsigned)m.ref_off, kRsrcWord3);
+  b.g = __builtin_amdgcn_make_buffer_rsrc(p + 9 * pb, (short)0, (int)(unsigned)(m.ref_off - 9 * pb),
+                                          kRsrcWord3);
+  b.ref = __builtin_amdgcn_make_buffer_rsrc(p + m.ref_off, (short)0, (int)(unsigned)m.ref_bytes,
                                             kRsrcWord3);
   return b;
 }
@@ -187,7 +188,8 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
 #pragma unroll
     for (int q = 0; q < 9; ++q) d.v[9 + q] = bld(sb.g, off, (unsigned)q * pb, (S *)nullptr);
     if (ST == ST_F32_LOCAL) {
-      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(sb.ref, (int)(cell * 2u), 0, 0);
+      const unsigned rc = (unsigned)(map_row(row_of(k)) * m.rpitch + xc);
+      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(sb.ref, (int)(rc * 2u), 0, 0);
       d.rb = (float)__builtin_bit_cast(_Float16, h);
     }
   };
@@ -323,7 +325,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     if (ST == ST_F32_LOCAL)
       __builtin_amdgcn_raw_buffer_store_b16(
           __builtin_bit_cast(unsigned short, (_Float16)rn_0[c]), db.ref,
-          (int)((inner ? own : (unsigned)(ny * pitch + lane)) * 2u), 0, 0);
+          (int)((unsigned)(inner ? r * m.rpitch + x : ny * m.rpitch + lane) * 2u), 0, 0);
 
     constexpr int kx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ky[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -548,7 +550,7 @@ __global__ void k_init(Model m, void *__restrict__ dst_v, const double *__restri
   if (ST == ST_F32_GLOBAL) rf = m.rho_ref;
   if (ST == ST_F32_LOCAL) {
     rf = (double)ref_of(r);
-    ref[idx] = (_Float16)(float)rf;
+    ref[(long long)y * m.rpitch + x] = (_Float16)(float)rf;
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -571,7 +573,8 @@ __global__ void k_plane_to(Model m, const void *__restrict__ src_v, int q, doubl
   const int x = (int)(c % m.nx), y = (int)(c / m.nx);
   const long long idx = (long long)y * m.pitch + x;
   const int i = q < 9 ? q : q - 9;
-  double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  double rf = ST == ST_F64 ? 0.0
+                           : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[(long long)y * m.rpitch + x]);
   if (q >= 9) rf *= m.cvT_ref;
   out[c] = (double)src[q * m.plane + idx] + wgt<double>(i) * rf;
 }
@@ -587,7 +590,8 @@ __global__ void k_plane_from(Model m, void *__restrict__ dst_v, int q, const dou
   const int x = (int)(c % m.nx), y = (int)(c / m.nx);
   const long long idx = (long long)y * m.pitch + x;
   const int i = q < 9 ? q : q - 9;
-  double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  double rf = ST == ST_F64 ? 0.0
+                           : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[(long long)y * m.rpitch + x]);
   if (q >= 9) rf *= m.cvT_ref;
   dst[q * m.plane + idx] = (S)(in[c] - wgt<double>(i) * rf);
 }
@@ -599,7 +603,7 @@ __global__ void k_ref_from_rho(Model m, void *__restrict__ dst_v, const double *
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const int x = (int)(c % m.nx), y = (int)(c / m.nx);
-  ref[(long long)y * m.pitch + x] = (_Float16)ref_of(rho[c]);
+  ref[(long long)y * m.rpitch + x] = (_Float16)ref_of(rho[c]);
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks,
@@ -708,7 +712,8 @@ __global__ void k_fd2(Model m, const double *__restrict__ mom, const double *__r
   S *dst = (S *)dst_v;
   const _Float16 *ref = (const _Float16 *)((const char *)dst_v + ref_plane_offset(m, ST));
   const long long idx = (long long)y * m.pitch + x;
-  const double rf = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[idx]);
+  const double rf = ST == ST_F64 ? 0.0
+                                 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)(float)ref[(long long)y * m.rpitch + x]);
   const double cvT = m.cv * Tn;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {

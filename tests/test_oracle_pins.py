@@ -205,16 +205,27 @@ def test_force_wall_mirror_ghost():
     Fx, Fy = oracle.sc_force_field(psi, psi ** 2, -1.0, wall_x=True)
     x0 = (1 / 3) * (psi[0, 1] - psi[0, 0]) + 2 * (1 / 12) * (psi[0, 1] - psi[0, 0])
     assert Fx[3, 0] == pytest.approx(psi[0, 0] * x0, rel=1e-14)
+    # the same along y, at the bottom and top walls (a periodic wrap would
+    # put the far row's psi there instead)
+    psy = psi.T.copy()  # varies in y only
+    Fx, Fy = oracle.sc_force_field(psy, psy ** 2, -1.0, wall_y=True)
+    y0 = (1 / 3 + 2 / 12) * (psy[1, 0] - psy[0, 0])
+    yt = (1 / 3 + 2 / 12) * (psy[n - 1, 0] - psy[n - 2, 0])
+    assert Fy[0, 3] == pytest.approx(psy[0, 0] * y0, rel=1e-14)
+    assert Fy[n - 1, 3] == pytest.approx(psy[n - 1, 0] * yt, rel=1e-14)
 
 
-def test_force_long_wave_limit():
-    """Below Eq. (4): F ~ -grad(p_EOS - rho c_s^2) for smooth fields, with
-    an error that falls as the square of the wavenumber."""
+@pytest.mark.parametrize("beta", [1.0, 0.0, 0.4])
+def test_force_long_wave_limit(beta):
+    """Below Eq. (4): F ~ -grad(p_EOS - rho c_s^2) for smooth fields, for any
+    mixing weight beta of Eq. (4), with an error that falls as the square of
+    the wavenumber."""
     T0 = 0.9 * inputs.cs_tc()
     errs = []
     for n in (64, 128):
         p = inputs.base_params(n, 4, T0)
         p["eos_fixed_T"] = True
+        p["beta"] = beta
         x = np.arange(n)
         rho1 = 0.12 + 0.02 * np.sin(2 * np.pi * x / n)
         rho = np.tile(rho1[None, :], (4, 1))
@@ -562,3 +573,41 @@ def test_plain_treatment_leaves_eos_domain_when_coupled():
     o.init_fields(rho, T)
     o.step(400, CORRECTED)
     assert o.totals()[5] == 0
+
+
+def test_cv_only_scales_the_energy():
+    """c_v cancels (g^eq = cv T f^eq, T = sum g / (rho cv), C_i ~ cv T): the
+    density and temperature after 300 steps of the coupled droplet do not
+    depend on it, while the energy scales with it."""
+    p, rho, T = inputs.static_droplet(nx=32, ny=32, radius=8, seed=9)
+    out = {}
+    for cv in (1.0, 2.5):
+        q = dict(p, cv=cv)
+        o = Oracle(q)
+        o.init_fields(rho, T)
+        assert o.step(300, CORRECTED) == 0
+        out[cv] = (o.moments(), o.totals()[1])
+    for a, b in zip(out[1.0][0], out[2.5][0]):
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(a).max())
+    assert out[2.5][1] == pytest.approx(2.5 * out[1.0][1], rel=1e-12)
+
+
+def test_density_wave_is_carried_by_a_uniform_flow():
+    """Galilean advection: a small density wave on a uniform flow u0 splits
+    into two sound waves whose common phase travels with the flow, so the
+    Fourier mode's phase after t steps is -k u0 t (the amplitude follows
+    cos(k c_s t)); single phase, periodic."""
+    nx, ny, u0, t = 64, 4, 0.05, 10
+    p = inputs.base_params(nx, ny, 1.0)
+    p["G"] = 0.0
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    rho = np.tile(1.0 + 1e-4 * np.cos(k * x), (ny, 1))
+    o = Oracle(p)
+    o.init_fields(rho, np.ones((ny, nx)), ux=np.full((ny, nx), u0))
+    o.step(t, CORRECTED)
+    mode = np.fft.fft(o.moments()[0].mean(axis=0))[1]
+    phase = np.angle(mode)
+    assert phase == pytest.approx(-k * u0 * t, rel=0.05)
+    amp = np.abs(mode) / (1e-4 * nx / 2)
+    assert amp == pytest.approx(np.cos(k * t / math.sqrt(3)), rel=0.05)
