@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-lattice batch section")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state (residual) section")
-    ap.add_argument("--steady-cases", type=int, default=16)
+    ap.add_argument("--steady-cases", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
     return ap.parse_args()

@@ -96,7 +96,17 @@ typedef struct {
   double gx, gy;        /* body acceleration; force rho * (gx, gy) */
   int wall_x, wall_y;   /* 0: periodic; 1: walls halfway outside the
                            first and last node (f bounces back; the psi
-                           ghost mirrors the boundary node) */
+                           ghost mirrors the boundary node).  wall_x = 2:
+                           open channel (Sec. III.A states only uniform
+                           inflow and fully developed outflow): inlet
+                           halfway left of the first column (f bounces
+                           back with the momentum of (u_in, 0); g
+                           anti-bounces back with the inlet equilibrium's
+                           even part at T_left, or bounces back when the
+                           left side is adiabatic), outlet halfway right of
+                           the last column (anti-bounce-back holding
+                           rho_out with the node's own velocity and
+                           energy) */
   int thermal_left, thermal_right, thermal_bottom, thermal_top;
                         /* LBM_THERMAL_DIRICHLET: g anti-bounces back
                            with the wall value rho cv T_w; ADIABATIC: g
@@ -109,6 +119,8 @@ typedef struct {
   int precision;        /* LBM_FP64, LBM_FP32_DEV or LBM_FP32_LOCAL */
   double rho_ref, T_ref;/* deviation shifts: rho_ref for LBM_FP32_DEV,
                            T_ref for both FP32 forms */
+  double u_in, rho_out; /* open channel (wall_x = 2): inlet velocity and
+                           outlet density (> 0) */
 } lbm_params;
 
 typedef struct lbm_ctx *lbm_handle;

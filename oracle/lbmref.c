@@ -47,6 +47,18 @@
  *     Eq. (23)); u and rho are those of time t for both stages.  Beyond a
  *     Dirichlet wall the temperature ghost is 2 T_w - T(boundary node),
  *     beyond an adiabatic wall T(boundary node); rho mirrors;
+ *   - open channel (wall_x = 2; the paper states inlet and outlet only as
+ *     uniform inflow and fully developed outflow): the inlet sits halfway
+ *     left of the first column, where f bounces back with the momentum of
+ *     the inlet velocity, f_ib = f_i* - 2 w_i rho (e_i . u_in)/c_s^2, and
+ *     g anti-bounces back with the inlet equilibrium's even part,
+ *     g_ib = -g_i* + 2 w_i cv rho T_in (1 + 4.5 (e_i.u_in)^2 - 1.5 u_in^2)
+ *     (bounces back when the left side is adiabatic); the outlet sits
+ *     halfway right of the last column and holds the density rho_out with
+ *     the node's own velocity and temperature (zero gradient) by
+ *     anti-bounce-back, f_ib = -f_i* + 2 w_i rho_out (1 + 4.5 (e_i.u)^2 -
+ *     1.5 u^2), g_ib = -g_i* + 2 w_i cv rho T (1 + 4.5 (e_i.u)^2 - 1.5 u^2);
+ *     psi and the finite-difference temperature mirror there;
  *   - walls sit halfway between nodes; f bounces back; g bounces back
  *     (adiabatic) or anti-bounces back with the wall value rho(x) cv T_w
  *     (Dirichlet); the pseudopotential ghost beyond a wall mirrors the
@@ -334,6 +346,25 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
         int xn = x + EX[i], yn = y + EY[i];
         int out_x = (xn < 0 || xn >= nx), out_y = (yn < 0 || yn >= ny);
         int hit_y = out_y && p->wall_y, hit_x = out_x && p->wall_x;
+        int open = p->wall_x == 2;
+        if (open && hit_x && !hit_y) {
+          int o = opposite(i);
+          if (xn >= nx) { /* outlet */
+            double eu = EX[i] * ux + EY[i] * uy;
+            double even = 1.0 + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy);
+            h->f2[PL(h, o) + c] = -fs + 2.0 * W[i] * p->rho_out * even;
+            h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * cvT * r * even;
+            continue;
+          }
+          double eu = EX[i] * p->u_in; /* inlet */
+          h->f2[PL(h, o) + c] = fs - 2.0 * W[i] * r * eu / CS2;
+          if (p->thermal_left == LBMREF_THERMAL_DIRICHLET)
+            h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * p->cv * r * p->T_left *
+                                            (1.0 + 4.5 * eu * eu - 1.5 * p->u_in * p->u_in);
+          else
+            h->g2[PL(h, o) + c] = gs;
+          continue;
+        }
         if (hit_y || hit_x) {
           int o = opposite(i);
           int thermal;

@@ -34,10 +34,16 @@ typedef struct {
   double T_eos;
   double cv;                /* specific heat in g^eq = cv T f^eq */
   double gx, gy;            /* body acceleration: force rho*(gx, gy) */
-  int wall_x, wall_y;       /* 0 periodic, 1 halfway bounce-back walls */
+  int wall_x, wall_y;       /* 0 periodic, 1 halfway bounce-back walls;
+                               wall_x = 2: open, inlet on the left (velocity
+                               (u_in, 0), temperature T_left), outlet on the
+                               right (density rho_out, zero gradient of u
+                               and T) */
   int thermal_left, thermal_right, thermal_bottom, thermal_top; /* LBMREF_THERMAL_* */
   double T_left, T_right, T_bottom, T_top;  /* Dirichlet wall temperatures */
   int psi_policy;           /* 0 clamp psi to 0 and count, 1 also flag an error */
+  double u_in;              /* inlet velocity (wall_x = 2) */
+  double rho_out;           /* outlet density (wall_x = 2) */
 } lbmref_params;
 
 typedef struct lbmref_ctx *lbmref_handle;

@@ -34,6 +34,8 @@ class _Params(ctypes.Structure):
         ("T_left", ctypes.c_double), ("T_right", ctypes.c_double),
         ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
         ("psi_policy", ctypes.c_int),
+        ("u_in", ctypes.c_double),
+        ("rho_out", ctypes.c_double),
     ]
 
 
@@ -89,12 +91,15 @@ def make_params(cfg):
     p.cv = float(cfg.get("cv", 1.0))
     p.gx = float(cfg.get("gx", 0.0))
     p.gy = float(cfg.get("gy", 0.0))
-    p.wall_x = int(bool(cfg.get("wall_x", False)))
+    wx = cfg.get("wall_x", False)
+    p.wall_x = 2 if (wx == "open" or (not isinstance(wx, bool) and wx == 2)) else int(bool(wx))
     p.wall_y = int(bool(cfg.get("wall_y", False)))
     for side in ("left", "right", "bottom", "top"):
         setattr(p, "thermal_" + side, _THERMAL[cfg.get("thermal_" + side, "dirichlet")])
         setattr(p, "T_" + side, float(cfg.get("T_" + side, 0.0)))
     p.psi_policy = int(cfg.get("psi_policy", 0))
+    p.u_in = float(cfg.get("u_in", 0.0))
+    p.rho_out = float(cfg.get("rho_out", 1.0))
     return p
 
 

@@ -34,12 +34,13 @@ struct Model {
   double a, b, R, T_eos;
   double cv, inv_cv;
   double gx, gy;
-  int wall_x, wall_y;
+  int wall_x, wall_y;        // wall_x: 0 periodic, 1 walls, 2 inlet (left) / outlet (right)
   int thermal[4];            // left, right, bottom, top: 0 Dirichlet, 1 adiabatic
   double wall_E[4];          // cv * T_w per wall (multiplied by the node's rho)
   double rho_ref;            // ST_F32_GLOBAL density shift
   double cvT_ref;            // cv * T_ref: energy shift per unit reference density
   double lam_per_rho;        // (tau_g - 1/2) cv c_s^2: conductivity over density
+  double u_in, rho_out;      // open channel (wall_x == 2): inlet velocity, outlet density
   double T_wall[4];          // wall temperatures (finite-difference treatment)
 };
 

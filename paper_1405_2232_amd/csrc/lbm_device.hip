@@ -402,8 +402,26 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
                              : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
                                                     : (double)rn_0[c] * m.cvT_ref);
         const C g_abb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
-        const C g_out = (stays || th != 0) ? gs + sh * cvTr : g_abb;
-        const C f_out = fs + sh;
+        C g_out = (stays || th != 0) ? gs + sh * cvTr : g_abb;
+        C f_out = fs + sh;
+        if (m.wall_x == 2 && !stays && !hy) {
+          const double refF = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rb_old);
+          const double refFn = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rn_0[c]);
+          if (exi > 0) {
+            // outlet: density rho_out, the node's own velocity and energy
+            const C eu = C(exi) * ux + C(eyi) * uy;
+            const C even = C(1) + C(4.5) * eu * eu - C(1.5) * uu;
+            f_out = -fs + wi * (C(2) * (C)m.rho_out * even - (C)(refF + refFn));
+            g_out = -gs + wi * (C(2) * Es * even - (C)(refE + refEn));
+          } else {
+            // inlet: bounce-back carrying the inlet momentum; Dirichlet g
+            // with the inlet equilibrium's even part
+            const C eui = C(exi) * (C)m.u_in;
+            f_out = fs + sh - C(6) * wi * rs * eui;
+            if (th == 0)
+              g_out = -gs + wi * (C)(2.0 * mm.rho * wE * (1.0 + 3.0 * m.u_in * m.u_in) - refE - refEn);
+          }
+        }
         const unsigned q = stays ? (unsigned)i : (unsigned)ko[i];
         const unsigned cell = !inner ? dummy : (stays ? (unsigned)(row * pitch + col) : own);
         bst(db.f, cell * sz + q * pb, 0u, (S)f_out);

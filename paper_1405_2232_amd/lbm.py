@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
         ("psi_policy", ctypes.c_int),
         ("precision", ctypes.c_int), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
     ]
 
 
@@ -131,12 +132,15 @@ def make_params(cfg, precision="fp64", rho_ref=None, T_ref=None):
     p.T_eos = float(cfg.get("T_eos", 0.0))
     p.cv = float(cfg.get("cv", 1.0))
     p.gx, p.gy = float(cfg.get("gx", 0.0)), float(cfg.get("gy", 0.0))
-    p.wall_x = int(bool(cfg.get("wall_x", False)))
+    wx = cfg.get("wall_x", False)
+    p.wall_x = 2 if (wx == "open" or (not isinstance(wx, bool) and wx == 2)) else int(bool(wx))
     p.wall_y = int(bool(cfg.get("wall_y", False)))
     for side in ("left", "right", "bottom", "top"):
         setattr(p, "thermal_" + side, _THERMAL[cfg.get("thermal_" + side, "dirichlet")])
         setattr(p, "T_" + side, float(cfg.get("T_" + side, 0.0)))
     p.psi_policy = int(cfg.get("psi_policy", 0))
+    p.u_in = float(cfg.get("u_in", 0.0))
+    p.rho_out = float(cfg.get("rho_out", 1.0))
     p.precision = _PREC[precision]
     p.rho_ref = float(rho_ref if rho_ref is not None else cfg.get("rho_ref", 0.0))
     p.T_ref = float(T_ref if T_ref is not None else cfg.get("T_ref", 0.0))

@@ -50,13 +50,18 @@ def test_warm_start_against_cold_start():
         "steps cold", cs, "warm", wsum)
     assert nw >= nc
     assert wsum <= cs
-    # the same steady state: both solves stop at a one-step residual r while
-    # the slowest mode (about a decade of r per 1e5 steps, e-folding over
-    # tau ~ 4e4 steps) still moves the fields by up to ~ r tau ~ 4e-3
-    # relative, so the two end states agree to that order, not to rounding
+    # the same steady state, up to what is not unique: with periodic x a
+    # droplet may settle anywhere along x (a continuous family of steady
+    # states), so the density is compared as a sorted set of values and the
+    # temperature by its x-average; both solves also stop at a one-step
+    # residual r while the slowest mode (a decade of r per ~1e5 steps,
+    # e-folding over tau ~ 4e4 steps) still moves the fields by up to
+    # ~ r tau ~ 4e-3 relative
     both = [i for i in range(len(test)) if cold["steps"][i] is not None and warm["steps"][i] is not None]
     for i in both:
-        dr = float(np.mean(np.abs(warm["fields"][i][0] - cold["fields"][i][0])))
-        dT = float(np.max(np.abs(warm["fields"][i][1] - cold["fields"][i][1])))
-        say("case", i, "warm vs cold steady state: mean |d rho|", dr, "max |d T|", dT)
+        rw, rc_ = warm["fields"][i][0], cold["fields"][i][0]
+        dr = float(np.mean(np.abs(np.sort(rw.ravel()) - np.sort(rc_.ravel()))))
+        dT = float(np.max(np.abs(warm["fields"][i][1].mean(axis=1) - cold["fields"][i][1].mean(axis=1))))
+        say("case", i, "warm vs cold steady state: sorted |d rho|", dr, "x-mean |d T|", dT,
+            "pointwise mean |d rho|", float(np.mean(np.abs(rw - rc_))))
         assert dr < 2e-3 and dT < 1e-3

@@ -13,8 +13,13 @@ import pytest
 import oracle.build as _build
 import oracle.lbmref as _ref
 
+import test_oracle_channel as channel
 import test_oracle_fd as fd
 import test_oracle_pins as pins
+
+
+def _channel_poiseuille():
+    channel.test_poiseuille_flux_outlet_density_and_profile()
 
 SRC = os.path.join(os.path.dirname(_build.__file__), "lbmref.c")
 HDR = os.path.join(os.path.dirname(_build.__file__), "lbmref.h")
@@ -90,7 +95,8 @@ MUTATIONS = [
      "Fy[c] += h->rho[c] * p->gy;", "Fy[c] -= h->rho[c] * p->gy;",
      [pins.test_momentum_budget_with_gravity]),
     ("adiabatic wall anti-bounces back",
-     "          else\n            h->g2[PL(h, o) + c] = gs;", "          else\n            h->g2[PL(h, o) + c] = -gs;",
+     "r * Tw;\n          else\n            h->g2[PL(h, o) + c] = gs;",
+     "r * Tw;\n          else\n            h->g2[PL(h, o) + c] = -gs;",
      [pins.test_adiabatic_walls_conserve_energy]),
     ("Carnahan-Starling numerator with + eta^3",
      "double num = 1.0 + eta + eta * eta - eta * eta * eta;",
@@ -119,6 +125,13 @@ MUTATIONS = [
     ("finite-difference Laplacian without the factor 2",
      "lapT += 2.0 * w * (Tn - T[c]);", "lapT += w * (Tn - T[c]);",
      [fd.test_one_step_matches_independent_numpy]),
+    ("inlet bounce-back without the inlet momentum",
+     "h->f2[PL(h, o) + c] = fs - 2.0 * W[i] * r * eu / CS2;", "h->f2[PL(h, o) + c] = fs;",
+     [_channel_poiseuille]),
+    ("outlet anti-bounce-back with the wrong sign",
+     "h->f2[PL(h, o) + c] = -fs + 2.0 * W[i] * p->rho_out * even;",
+     "h->f2[PL(h, o) + c] = fs + 2.0 * W[i] * p->rho_out * even;",
+     [_channel_poiseuille]),
     ("finite-difference Dirichlet ghost equal to the wall value",
      "return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;\n  }\n  if (outx && p->wall_x) {",
      "return th == LBMREF_THERMAL_DIRICHLET ? Tw : v;\n  }\n  if (outx && p->wall_x) {",
