@@ -208,8 +208,9 @@ typedef struct lbm_batch_ctx *lbm_batch_handle;
 /* Device bytes for a batch of `count` lattices with parameters p[0..count). */
 int lbm_batch_workspace_bytes(int count, const lbm_params *p, size_t *bytes);
 
-/* Bind a caller-owned workspace and stream; all p[i].precision must agree.
- * Uploads the lattice tables (synchronous). */
+/* Bind a caller-owned workspace and stream; all p[i].precision must agree
+ * and no lattice may be an open channel (wall_x = 2).  Uploads the lattice
+ * tables (synchronous). */
 int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t bytes,
                      void *hip_stream, lbm_batch_handle *out);
 

@@ -45,7 +45,10 @@ struct Model {
 };
 
 // What one launch of the tile kernel does.
-enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1 };
+// MODE_STEP_OPEN is MODE_STEP with the inlet/outlet code of the open
+// channel compiled in (kept out of the other lattices' kernels, where its
+// extra live values would push the row buffers into scratch memory)
+enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_OPEN = 2 };
 
 // Output/side buffers of a moments launch (all optional).
 struct MomentsOut {

@@ -404,7 +404,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         const C g_abb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
         C g_out = (stays || th != 0) ? gs + sh * cvTr : g_abb;
         C f_out = fs + sh;
-        if (m.wall_x == 2 && !stays && !hy) {
+        if (MODE == MODE_STEP_OPEN && m.wall_x == 2 && !stays && !hy) {
           const double refF = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rb_old);
           const double refFn = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rn_0[c]);
           if (exi > 0) {
@@ -430,7 +430,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     }
   };
 
-  if (PF >= 2 && MODE == MODE_STEP) {
+  if (PF >= 2 && MODE != MODE_MOMENTS) {
     // PF + 1 row buffers in rotating roles: at row k the buffers hold rows
     // k (collide), k + 1 (psi) and k + 2 .. k + PF (loads in flight).  The
     // loop is unrolled over a full rotation so that every buffer index is a
@@ -804,6 +804,10 @@ static hipError_t launch_tile_st(const Model &m, const Tiling &t, int st, const 
 hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *cc, hipStream_t s) {
   MomentsOut mo{};
+  if (m.wall_x == 2) {
+    if (t.pf >= 2) return launch_tile_st<MODE_STEP_OPEN, 2>(m, t, st, src, dst, treatment, cc, mo, s);
+    return launch_tile_st<MODE_STEP_OPEN, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+  }
   if (t.pf >= 3) return launch_tile_st<MODE_STEP, 3>(m, t, st, src, dst, treatment, cc, mo, s);
   if (t.pf == 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
   return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);

@@ -47,8 +47,8 @@ def test_channel_parity(treatment, precision):
 def _nusselt_fully_developed(p, treatment, steps):
     """Nu(x) = D_h q_w / (lambda (T_w - T_b)) at the top wall, D_h = 2 H,
     the wall gradient from the two nodes next to the wall, T_b the
-    mass-flux-weighted bulk temperature; averaged over the last quarter of
-    the channel before the outlet's last 10 columns."""
+    mass-flux-weighted bulk temperature; averaged over the third quarter of
+    the channel (thermally developed, away from the outlet's influence)."""
     from paper_1405_2232_amd.lbm import Lattice
     nx, ny = p["nx"], p["ny"]
     g = Lattice(p, "fp64")
@@ -58,7 +58,7 @@ def _nusselt_fully_developed(p, treatment, steps):
     Tw = p["T_top"]
     Tb = (r * ux * T).sum(0) / (r * ux).sum(0)
     nu = 2 * ny * (T[-1] - T[-2]) / (Tw - Tb)
-    return float(np.mean(nu[3 * nx // 4: nx - 10]))
+    return float(np.mean(nu[nx // 2: 3 * nx // 4]))
 
 
 def test_table1_fully_developed_nusselt():
@@ -67,8 +67,14 @@ def test_table1_fully_developed_nusselt():
     for case in ("A", "B"):
         p = channel(500, 60, case)
         for tr in (FD_RK2, CORRECTED):
-            out[(case, tr)] = _nusselt_fully_developed(p, tr, 60000)
+            out[(case, tr)] = _nusselt_fully_developed(p, tr, 150000)
     say("channel Nu: FD A/B", out[("A", FD_RK2)], out[("B", FD_RK2)], "corrected A/B",
         out[("A", CORRECTED)], out[("B", CORRECTED)], "printed", gold["nu"])
+    # the paper's own values sit 0.4 % (A) and 1 % (B) from the analytic
+    # ones; these are held to 2.5 % of the printed values and 2 % of the
+    # analytic ones
     for case in ("A", "B"):
-        assert abs(out[(case, FD_RK2)] - gold["nu"]["finite_difference_eq26"][case]) <= 0.02 * gold["nu"]["analytic"][case]
+        for tr, key in ((FD_RK2, "finite_difference_eq26"), (CORRECTED, "corrected_eq24")):
+            printed = gold["nu"][key][case]
+            assert abs(out[(case, tr)] - printed) <= 0.025 * printed, (case, tr)
+        assert abs(out[(case, FD_RK2)] - gold["nu"]["analytic"][case]) <= 0.02 * gold["nu"]["analytic"][case]
