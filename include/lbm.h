@@ -121,6 +121,10 @@ typedef struct {
                            T_ref for both FP32 forms */
   double u_in, rho_out; /* open channel (wall_x = 2): inlet velocity and
                            outlet density (> 0) */
+  int phi_divu;         /* 1: LBM_FD_RK2 keeps the term phi div u of
+                           Eq. (5), phi = -T (dp_EOS/dT)_rho, which the
+                           paper's Eq. (6) drops; the LB treatments ignore
+                           it.  0 or 1. */
 } lbm_params;
 
 typedef struct lbm_ctx *lbm_handle;

@@ -47,6 +47,11 @@
  *     Eq. (23)); u and rho are those of time t for both stages.  Beyond a
  *     Dirichlet wall the temperature ghost is 2 T_w - T(boundary node),
  *     beyond an adiabatic wall T(boundary node); rho mirrors;
+ *   - with phi_divu the finite-difference treatment keeps the term
+ *     phi div u of Eq. (5), phi = -T (dp_EOS/dT)_rho, in K(T) as
+ *     phi div u / (rho cv), div u by the same isotropic gradient (the
+ *     velocity ghost beyond a wall is the boundary node's velocity
+ *     reversed, for a no-slip wall halfway out);
  *   - open channel (wall_x = 2; the paper states inlet and outlet only as
  *     uniform inflow and fully developed outflow): the inlet sits halfway
  *     left of the first column, where f bounces back with the momentum of
@@ -421,6 +426,25 @@ static double ghost(lbmref_handle h, const double *phi, int x, int y, int is_T) 
   return v;
 }
 
+/* (dp_EOS/dT) at fixed rho: Carnahan-Starling rho R Z(eta), ideal rho R */
+static double dp_dT(const lbmref_params *p, double rho) {
+  if (p->eos == LBMREF_EOS_IDEAL) return rho * p->R;
+  double eta = p->b * rho / 4.0;
+  double num = 1.0 + eta + eta * eta - eta * eta * eta;
+  double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);
+  return rho * p->R * num / den;
+}
+
+/* velocity component at (x, y) one node beyond the lattice at most:
+ * periodic wrap, or the boundary node's value reversed beyond a wall */
+static double u_ghost(lbmref_handle h, const double *u, int x, int y) {
+  const lbmref_params *p = &h->p;
+  int outx = x < 0 || x >= p->nx, outy = y < 0 || y >= p->ny;
+  double v = ghost(h, u, x, y, 0);
+  if ((outx && p->wall_x) || (outy && p->wall_y)) v = -v;
+  return v;
+}
+
 /* K(T) of Eq. (26) at every node, with u and rho of time t */
 static void fd_rhs(lbmref_handle h, const double *T, double *K) {
   const lbmref_params *p = &h->p;
@@ -443,6 +467,16 @@ static void fd_rhs(lbmref_handle h, const double *T, double *K) {
       double lam = lam_per_rho * h->rho[c];
       double div = lam * lapT + gLx * gTx + gLy * gTy;
       K[c] = -(h->ux[c] * gTx + h->uy[c] * gTy) + div / (h->rho[c] * p->cv);
+      if (p->phi_divu) {
+        double du = 0.0;
+        for (int i = 1; i < 9; ++i) {
+          double w = w_sc(i);
+          du += w * (u_ghost(h, h->ux, x + EX[i], y + EY[i]) * EX[i] +
+                     u_ghost(h, h->uy, x + EX[i], y + EY[i]) * EY[i]);
+        }
+        double phi = -T[c] * dp_dT(p, h->rho[c]);
+        K[c] += phi * du / (h->rho[c] * p->cv);
+      }
     }
   }
 }

@@ -36,6 +36,7 @@ class _Params(ctypes.Structure):
         ("psi_policy", ctypes.c_int),
         ("u_in", ctypes.c_double),
         ("rho_out", ctypes.c_double),
+        ("phi_divu", ctypes.c_int),
     ]
 
 
@@ -100,6 +101,7 @@ def make_params(cfg):
     p.psi_policy = int(cfg.get("psi_policy", 0))
     p.u_in = float(cfg.get("u_in", 0.0))
     p.rho_out = float(cfg.get("rho_out", 1.0))
+    p.phi_divu = int(bool(cfg.get("phi_divu", False)))
     return p
 
 

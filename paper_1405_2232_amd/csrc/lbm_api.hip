@@ -132,6 +132,7 @@ int validate(const lbm_params *p) {
     if (th[k] != LBM_THERMAL_DIRICHLET && th[k] != LBM_THERMAL_ADIABATIC) return LBM_EINVAL;
   if (p->psi_policy != 0 && p->psi_policy != 1) return LBM_EINVAL;
   if (p->wall_x != 0 && p->wall_x != 1 && p->wall_x != 2) return LBM_EINVAL;
+  if (p->phi_divu != 0 && p->phi_divu != 1) return LBM_EINVAL;
   if (p->wall_x == 2 && (!(p->rho_out > 0.0) || !isfinite(p->rho_out) || !isfinite(p->u_in)))
     return LBM_EINVAL;
   if (p->wall_y != 0 && p->wall_y != 1) return LBM_EINVAL;
@@ -190,6 +191,7 @@ Model make_model(const lbm_params *p, const Layout &L) {
   m.lam_per_rho = (p->tau_g - 0.5) * p->cv * (1.0 / 3.0);
   m.u_in = p->u_in;
   m.rho_out = p->rho_out;
+  m.phi_divu = p->phi_divu != 0;
   if (p->precision == LBM_FP32_DEV) m.rho_ref = p->rho_ref;
   if (p->precision != LBM_FP64) m.cvT_ref = p->cv * p->T_ref;
   return m;

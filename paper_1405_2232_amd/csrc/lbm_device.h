@@ -41,6 +41,7 @@ struct Model {
   double cvT_ref;            // cv * T_ref: energy shift per unit reference density
   double lam_per_rho;        // (tau_g - 1/2) cv c_s^2: conductivity over density
   double u_in, rho_out;      // open channel (wall_x == 2): inlet velocity, outlet density
+  int phi_divu;              // finite-difference treatment keeps phi div u (Eq. (5))
   double T_wall[4];          // wall temperatures (finite-difference treatment)
 };
 

@@ -681,10 +681,22 @@ __device__ inline double fd_T_ghost(const Model &m, double v, int x, int y, bool
   return v;
 }
 
-// K at node (x, y); Tval(c) gives the stage temperature at an in-lattice node
+// (dp_EOS/dT) at fixed rho: Carnahan-Starling rho R Z(eta), ideal rho R
+__device__ inline double dp_dT(const Model &m, double rho) {
+  if (m.eos == 1) return rho * m.R;
+  const double eta = 0.25 * m.b * rho;
+  const double om = 1.0 - eta;
+  return rho * m.R * (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om);
+}
+
+// K at node (x, y); Tval(c) gives the stage temperature at an in-lattice
+// node.  With m.phi_divu, K also carries phi div u / (rho cv) of Eq. (5),
+// phi = -T (dp_EOS/dT)_rho, div u by the same gradient stencil (the
+// velocity beyond a wall is the boundary node's, reversed)
 template <typename TV>
-__device__ inline double fd_K(const Model &m, const double *rho, double ux, double uy, int x, int y,
-                              long long c, TV Tval) {
+__device__ inline double fd_K(const Model &m, const double *rho, const double *uxa, const double *uya,
+                              int x, int y, long long c, TV Tval) {
+  const double ux = uxa[c], uy = uya[c];
   constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double Tc = Tval(c);
@@ -704,7 +716,21 @@ __device__ inline double fd_K(const Model &m, const double *rho, double ux, doub
     lap += 2.0 * w * (Tn - Tc);
   }
   const double div = m.lam_per_rho * rho[c] * lap + gLx * gTx + gLy * gTy;
-  return -(ux * gTx + uy * gTy) + div / (rho[c] * m.cv);
+  double K = -(ux * gTx + uy * gTy) + div / (rho[c] * m.cv);
+  if (m.phi_divu) {
+    double du = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+      const int xn = x + ex[i], yn = y + ey[i];
+      bool ox, oy;
+      const long long cn = fd_node(m, xn, yn, ox, oy);
+      const double sgn = ((ox && m.wall_x) || (oy && m.wall_y)) ? -1.0 : 1.0;
+      du += w * (sgn * uxa[cn] * ex[i] + sgn * uya[cn] * ey[i]);
+    }
+    K += -Tc * dp_dT(m, rho[c]) * du / (rho[c] * m.cv);
+  }
+  return K;
 }
 
 __global__ void k_fd1(Model m, const double *__restrict__ mom, double *__restrict__ k1) {
@@ -713,7 +739,7 @@ __global__ void k_fd1(Model m, const double *__restrict__ mom, double *__restric
   if (c >= n) return;
   const int x = (int)(c % m.nx), y = (int)(c / m.nx);
   const double *rho = mom, *ux = mom + n, *uy = mom + 2 * n, *T = mom + 3 * n;
-  k1[c] = fd_K(m, rho, ux[c], uy[c], x, y, c, [&](long long q) { return T[q]; });
+  k1[c] = fd_K(m, rho, ux, uy, x, y, c, [&](long long q) { return T[q]; });
 }
 
 template <int ST>
@@ -725,7 +751,7 @@ __global__ void k_fd2(Model m, const double *__restrict__ mom, const double *__r
   if (c >= n) return;
   const int x = (int)(c % m.nx), y = (int)(c / m.nx);
   const double *rho = mom, *ux = mom + n, *uy = mom + 2 * n, *T = mom + 3 * n;
-  const double k2 = fd_K(m, rho, ux[c], uy[c], x, y, c, [&](long long q) { return T[q] + k1[q]; });
+  const double k2 = fd_K(m, rho, ux, uy, x, y, c, [&](long long q) { return T[q] + k1[q]; });
   const double Tn = T[c] + 0.5 * (k1[c] + k2);
   S *dst = (S *)dst_v;
   const _Float16 *ref = (const _Float16 *)((const char *)dst_v + ref_plane_offset(m, ST));

@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("psi_policy", ctypes.c_int),
         ("precision", ctypes.c_int), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("phi_divu", ctypes.c_int),
     ]
 
 
@@ -141,6 +142,7 @@ def make_params(cfg, precision="fp64", rho_ref=None, T_ref=None):
     p.psi_policy = int(cfg.get("psi_policy", 0))
     p.u_in = float(cfg.get("u_in", 0.0))
     p.rho_out = float(cfg.get("rho_out", 1.0))
+    p.phi_divu = int(bool(cfg.get("phi_divu", False)))
     p.precision = _PREC[precision]
     p.rho_ref = float(rho_ref if rho_ref is not None else cfg.get("rho_ref", 0.0))
     p.T_ref = float(T_ref if T_ref is not None else cfg.get("T_ref", 0.0))

@@ -71,3 +71,18 @@ def test_switching_treatments_mid_run():
     st = g.get_state()
     f, gg = o.get_state()
     assert np.abs(st[:9] - f).max() < 1e-12 and np.abs(st[9:] - gg).max() < 1e-12
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_phi_divu_fd_parity(walls):
+    Tc = inputs.cs_tc()
+    p, rho, T = inputs.static_droplet(nx=70, ny=52, radius=13, seed=8)
+    p["phi_divu"] = True
+    if walls:
+        p.update(wall_x=True, wall_y=True, thermal_left="adiabatic", thermal_right="dirichlet",
+                 thermal_bottom="dirichlet", thermal_top="dirichlet", T_right=0.87 * Tc,
+                 T_bottom=0.84 * Tc, T_top=0.86 * Tc, gy=-1e-5)
+    say("case fd phi div u", walls)
+    g = gpu_run(p, rho, T, 800, FD_RK2)
+    o = oracle_run(p, rho, T, 800, FD_RK2)
+    compare_fp64(g.moments(), o.moments(), what=("fd phi div u", walls))

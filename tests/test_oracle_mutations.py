@@ -132,6 +132,9 @@ MUTATIONS = [
      "h->f2[PL(h, o) + c] = -fs + 2.0 * W[i] * p->rho_out * even;",
      "h->f2[PL(h, o) + c] = fs + 2.0 * W[i] * p->rho_out * even;",
      [_channel_poiseuille]),
+    ("phi div u with the wrong sign",
+     "K[c] += phi * du / (h->rho[c] * p->cv);", "K[c] -= phi * du / (h->rho[c] * p->cv);",
+     [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0)]),
     ("finite-difference Dirichlet ghost equal to the wall value",
      "return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;\n  }\n  if (outx && p->wall_x) {",
      "return th == LBMREF_THERMAL_DIRICHLET ? Tw : v;\n  }\n  if (outx && p->wall_x) {",
