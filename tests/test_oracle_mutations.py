@@ -99,8 +99,8 @@ MUTATIONS = [
      "r * Tw;\n          else\n            h->g2[PL(h, o) + c] = -gs;",
      [pins.test_adiabatic_walls_conserve_energy]),
     ("Carnahan-Starling numerator with + eta^3",
-     "double num = 1.0 + eta + eta * eta - eta * eta * eta;",
-     "double num = 1.0 + eta + eta * eta + eta * eta * eta;",
+     "double num = 1.0 + eta + eta * eta - eta * eta * eta;\n  double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);\n  return rho * p->R * T",
+     "double num = 1.0 + eta + eta * eta + eta * eta * eta;\n  double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);\n  return rho * p->R * T",
      [pins.test_cs_eos_critical_point]),
     ("velocity without the half force",
      "      double ux = (h->jx[c] + 0.5 * Fx[c]) / r;\n      double uy = (h->jy[c] + 0.5 * Fy[c]) / r;\n      h->ux[c] = ux;",
