@@ -189,7 +189,7 @@ int lbm_set_state(lbm_handle h, const double *state);
 int lbm_save(lbm_handle h, const char *path);
 int lbm_load(lbm_handle h, const char *path);
 
-/* Tile shape of the step kernel: bx columns per block (64, 128 or 256)
+/* Tile shape of the step kernel: bx columns per block (64, 128, 256 or 512)
  * and `rows` rows per block (>= 1).  The default comes from the lattice
  * size; an autotuner may pick another.  Results do not depend on it. */
 int lbm_set_tiling(lbm_handle h, int bx, int rows);

@@ -32,7 +32,7 @@ Tiling default_tiling(int nx, int ny, int precision) {
   (void)precision;
   // experiment knobs (environment) override the defaults
   const long long ebx = env_ll("LBM_BX", 0), erows = env_ll("LBM_ROWS", 0);
-  if (ebx == 64 || ebx == 128 || ebx == 256) t.bx = (int)ebx;
+  if (ebx == 64 || ebx == 128 || ebx == 256 || ebx == 512) t.bx = (int)ebx;
   if (erows >= 1) t.rows = (int)(erows < ny ? erows : ny);
   t.strips = (nx + t.bx - 3) / (t.bx - 2);
   t.bands = (ny + t.rows - 1) / t.rows;
@@ -73,17 +73,17 @@ bool compute_layout(const lbm_params *p, Layout *L) {
     // row length, the rows that concurrent blocks touch would all map to
     // the same HBM channel (measured 2.5x slower)
     L->rpitch = (int)(row + 128);
-    const long long body = (long long)p->ny * L->pitch + L->pitch + 256;
+    const long long body = (long long)p->ny * L->pitch + L->pitch + 512;
     L->ref_off = align_up((size_t)body * L->elem, kAlign);
-    L->ref_bytes = ((size_t)p->ny * L->rpitch + 256) * 2;
+    L->ref_bytes = ((size_t)p->ny * L->rpitch + 512) * 2;
   } else {
     // one plane per distribution, each ending in a 4 KiB pad: the pad
     // staggers the 18 streams of a row over HBM channels and holds the
     // slots that lanes owning no node store into (the kernels need at
-    // least 256 elements there)
+    // least 512 elements there)
     L->pitch = (int)row;
     long long pad = env_ll("LBM_PLANE_PAD", 16) * align_elems;
-    if (pad < 256) pad = 256;
+    if (pad < 512) pad = 512;
     L->plane = (long long)align_up((size_t)L->pitch * (size_t)p->ny, (size_t)align_elems) + pad;
     L->rpitch = L->pitch;
     L->ref_off = (size_t)L->plane * 18 * L->elem;
@@ -570,7 +570,7 @@ int lbm_load(lbm_handle h, const char *path) {
 
 int lbm_set_tiling(lbm_handle h, int bx, int rows) {
   if (!h) return LBM_EINVAL;
-  if (bx != 64 && bx != 128 && bx != 256) return LBM_EINVAL;
+  if (bx != 64 && bx != 128 && bx != 256 && bx != 512) return LBM_EINVAL;
   if (rows < 1) return LBM_EINVAL;
   if (rows > h->p.ny) rows = h->p.ny;
   h->t.bx = bx;

@@ -809,6 +809,9 @@ static hipError_t launch_tile_t(const Model &m, const Tiling &t, const void *src
     case 256:
       hipLaunchKernelGGL((k_tile<ST, 256, MODE, PF>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc, mo);
       break;
+    case 512:
+      hipLaunchKernelGGL((k_tile<ST, 512, MODE, PF>), dim3(grid), dim3(512), 0, s, m, t, src, dst, treatment, cc, mo);
+      break;
     default:
       return hipErrorInvalidValue;
   }

@@ -137,7 +137,7 @@ def test_tiling_invariance_bitwise(precision):
     p, rho, T = inputs.static_droplet(nx=150, ny=90, radius=20, seed=21)
     p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc)
     ref = None
-    for tiling in (None, (64, 1), (128, 3), (256, 7), (64, 90)):
+    for tiling in (None, (64, 1), (128, 3), (256, 7), (512, 5), (64, 90)):
         say("case tiling", precision, tiling)
         g = gpu_run(p, rho, T, 60, CORRECTED, precision=precision, tiling=tiling)
         s = g.get_state()
