@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--steady-cases", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="only summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, "
+                         "then WRITE_SIZE) into the step kernel's HBM traffic file")
     return ap.parse_args()
 
 
@@ -86,6 +89,58 @@ def copy_rate(nbytes):
 def copy_probe_only(nbytes):
     ms, gbs = copy_rate(nbytes)
     print(json.dumps({"copy_bytes": nbytes, "ms": round(ms, 5), "GBs": round(gbs, 1)}), flush=True)
+
+
+def _counter_rows(d):
+    """(kernel name, counter value) of every dispatch in the rocprofv3
+    counter-collection CSVs under directory d."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fp:
+            for r in csv.DictReader(fp):
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit("no counter_collection.csv under " + d)
+    return rows
+
+
+def traffic_summary(args):
+    """HBM bytes per step-kernel launch from a FETCH_SIZE and a WRITE_SIZE
+    run of this script.  Each counter is scaled by what it reads for the
+    1 GiB plain copy kernel the same run launches (1 GiB read, 1 GiB
+    written), then the per-launch mean over the step kernel's dispatches is
+    written with the hash of the kernel sources it was taken on."""
+    import re
+    step = re.compile(r"lbmdev::k_tile<(\d+), (\d+), 0, (\d+)>")
+    out = {"precision": args.precision, "nx": args.nx, "ny": args.ny,
+           "layout": "row-interleaved", "kernel_hash": kernel_hash()}
+    copy_kib = float(1 << 20)
+    for key, d in (("fetch", args.traffic_from[0]), ("write", args.traffic_from[1])):
+        rows = _counter_rows(d)
+        copies = [v for k, v in rows if "lbmdev::k_copy" in k]
+        steps = {}
+        for k, v in rows:
+            m = step.search(k)
+            if m:
+                steps.setdefault(m.group(0), []).append(v)
+        if not copies or not steps:
+            raise SystemExit("no copy or step-kernel dispatches in " + d)
+        name, vals = max(steps.items(), key=lambda kv: len(kv[1]))
+        scale = copy_kib / (sum(copies) / len(copies))
+        raw = sum(vals) / len(vals)
+        out["kernel"] = name
+        out[key + "_kib_raw"] = round(raw, 1)
+        out[key + "_scale"] = round(scale, 4)
+        out[key + "_bytes"] = int(raw * scale * 1024)
+        out[key + "_launches"] = len(vals)
+    out["bytes_per_launch"] = out["fetch_bytes"] + out["write_bytes"]
+    out["bytes_per_node"] = round(out["bytes_per_launch"] / (args.nx * args.ny), 1)
+    with open(TRAFFIC_FILE, "w") as fp:
+        json.dump(out, fp, indent=1)
+        fp.write("\n")
+    print(json.dumps(out), flush=True)
 
 
 def batch_section(steps, torch):
@@ -226,6 +281,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe_only(args.copy_probe)
+        return
+    if args.traffic_from:
+        traffic_summary(args)
         return
     import torch
     from paper_1405_2232_amd import inputs
