@@ -193,6 +193,20 @@ int lbm_load(lbm_handle h, const char *path);
  * and `rows` rows per block (>= 1).  The default comes from the lattice
  * size; an autotuner may pick another.  Results do not depend on it. */
 int lbm_set_tiling(lbm_handle h, int bx, int rows);
+
+/* Two steps per kernel launch (temporal blocking).  Where the lattice
+ * allows it (LBM_FP32_DEV or LBM_FP32_LOCAL storage, periodic in x, beta = 1
+ * in Eq. (4) or G = 0) lbm_step advances the plain and corrected treatments
+ * two steps per launch: the distributions of the intermediate time level
+ * stay on chip, which halves the HBM traffic per step.  The arithmetic of
+ * each step is the one-step kernel's.  `on` = 0 makes every step a
+ * one-step launch; `rows` (> 0) sets the rows per block of the two-step
+ * kernel, 0 keeps the current value.  Default: on, 8 rows.  A step that
+ * ends at a periodic check is always a one-step launch.
+ * lbm_get_step_pairing reports whether lbm_step will pair steps (`active`)
+ * and the rows per block.  LBM_EINVAL for a NULL handle or rows < 0. */
+int lbm_set_step_pairing(lbm_handle h, int on, int rows);
+int lbm_get_step_pairing(lbm_handle h, int *active, int *rows);
 int lbm_get_tiling(lbm_handle h, int *bx, int *rows);
 
 int lbm_destroy(lbm_handle h);

@@ -43,6 +43,22 @@ Tiling default_tiling(int nx, int ny, int precision) {
   return t;
 }
 
+// Two-step tiling: 256 lanes, strips of 250 owned columns, bands of `rows`
+// rows (8 by default: each band recomputes the first step on four extra
+// rows, so short bands cost arithmetic and long ones cost blocks).
+Tiling pair_tiling(int nx, int ny, int rows) {
+  Tiling t;
+  t.bx = 256;
+  t.strips = (nx + t.bx - 7) / (t.bx - 6);
+  t.rows = rows < ny ? rows : ny;
+  t.bands = (ny + t.rows - 1) / t.rows;
+  t.xcd = (int)env_ll("LBM_XCD", 1);
+  t.alt = 0;
+  t.nt = 0;
+  t.pf = 1;
+  return t;
+}
+
 long long env_ll(const char *name, long long dflt) {
   const char *s = getenv(name);
   if (!s || !*s) return dflt;
@@ -289,6 +305,9 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->st = storage_of(p);
   h->t = default_tiling(p->nx, p->ny, p->precision);
   h->tm = h->t;
+  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 8) > 0 ? (int)env_ll("LBM_PAIR_ROWS", 8) : 8);
+  h->pair_ok = h->st != lbmdev::ST_F64 && p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
+  h->pair_on = env_ll("LBM_PAIR", 1) != 0;
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char *)dev_workspace;
   h->buf[0] = h->ws + L.off_buf[0];
@@ -358,10 +377,20 @@ int lbm_step(lbm_handle h, int n, int treatment) {
   if (!h || n < 1) return LBM_EINVAL;
   if (!treatment_ok(treatment)) return LBM_EINVAL;
   if (!h->initialized) return LBM_ESTATE;
-  for (int k = 0; k < n; ++k) {
-    HIPCHK(one_step(h, treatment));
+  const bool pairs = h->pair_on && h->pair_ok && (treatment == LBM_PLAIN || treatment == LBM_CORRECTED);
+  for (int k = 0; k < n;) {
+    // two steps in one launch unless the first of them ends at a check
+    if (pairs && k + 1 < n && !(h->check_every > 0 && (h->steps + 1) % h->check_every == 0)) {
+      HIPCHK(lbmdev::launch_pair(h->m, h->tp, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
+                                 h->counters, h->stream));
+      h->steps += 2;
+      k += 2;
+    } else {
+      HIPCHK(one_step(h, treatment));
+      h->steps += 1;
+      k += 1;
+    }
     h->cur ^= 1;
-    h->steps += 1;
     if (h->check_every > 0 && h->steps % h->check_every == 0) {
       int rc = check(h);
       if (rc) return rc;
@@ -577,6 +606,20 @@ int lbm_set_tiling(lbm_handle h, int bx, int rows) {
   h->t.strips = (h->p.nx + bx - 3) / (bx - 2);
   h->t.rows = rows;
   h->t.bands = (h->p.ny + rows - 1) / rows;
+  return LBM_OK;
+}
+
+int lbm_set_step_pairing(lbm_handle h, int on, int rows) {
+  if (!h || rows < 0) return LBM_EINVAL;
+  h->pair_on = on != 0;
+  if (rows > 0) h->tp = lbmhost::pair_tiling(h->p.nx, h->p.ny, rows);
+  return LBM_OK;
+}
+
+int lbm_get_step_pairing(lbm_handle h, int *active, int *rows) {
+  if (!h || !active || !rows) return LBM_EINVAL;
+  *active = h->pair_on && h->pair_ok;
+  *rows = h->tp.rows;
   return LBM_OK;
 }
 

@@ -37,6 +37,7 @@ struct Layout {
 
 long long env_ll(const char *name, long long dflt);
 Tiling default_tiling(int nx, int ny, int precision);
+Tiling pair_tiling(int nx, int ny, int rows);
 int storage_of(const lbm_params *p);
 bool compute_layout(const lbm_params *p, Layout *L);
 bool fits_32bit(const Layout &L);
@@ -51,6 +52,9 @@ struct lbm_ctx {
   lbmdev::Model m;
   lbmdev::Tiling t;        // step tiling
   lbmdev::Tiling tm;       // moments tiling (fixed: sizes the partials buffer)
+  lbmdev::Tiling tp;       // two-step tiling
+  int pair_ok;             // the lattice admits two-step launches
+  int pair_on;             // lbm_step uses them
   int st;          // lbmdev::Storage
   hipStream_t stream;
   char *ws;

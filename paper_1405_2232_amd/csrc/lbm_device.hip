@@ -84,8 +84,15 @@ __device__ inline void node_psi(const Model &m, double rho, double E, double &ps
 }
 
 // The density reference of a node in ST_F32_LOCAL storage: rho rounded to
-// FP16 (every block that computes a node's rho gets the same bits).
-__device__ inline float ref_of(double rho) { return (float)(_Float16)(float)rho; }
+// FP32 and then to FP16 (every block that computes a node's rho gets the
+// same bits).  The empty asm keeps the two hardware conversions: without it
+// the pair of roundings is folded into one FP64-to-FP16 rounding done in
+// software, some thirty instructions.
+__device__ inline float ref_of(double rho) {
+  float f = (float)rho;
+  asm volatile("" : "+v"(f));
+  return (float)(_Float16)f;
+}
 
 // --- buffer addressing: one 32-bit byte offset per lane, plane offsets in SGPRs
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -132,6 +139,78 @@ struct Mom {
   double rho, E;
   C jx, jy;  // first moment of f
   C sf, sg;  // deviation sums (rho - ref, E - ref * cvT_ref)
+};
+
+// Post-collision values of a node: Eq. (1) with the forcing term, and
+// Eq. (7) or Eq. (24), with f_eq, g_eq = cv T f_eq and the forcing terms
+// expanded in e_i.u and e_i.F (arithmetic in C, on deviations from the
+// node's reference):
+//   f_i* = (1 - 1/tau_f) f_i + w_i [K_f + e.u (A_f + B_f e.u + 9 k_f e.F) + 3 k_f e.F]
+//   g_i* = (1 - 1/tau_g) g_i + w_i [K_g + e.u (A_g + B_g e.u) + k_c e.F]
+// A_f = 3 rho/tau_f, B_f = 4.5 rho/tau_f, K_f = (drho - 1.5 rho u.u)/tau_f -
+// 3 k_f u.F; A_g, B_g, K_g the same with rho cv T and dE; k_f = 1 -
+// 1/(2 tau_f); k_c = (1 - 1/(2 tau_g)) 3 cv T for Eq. (24), 0 for Eq. (7).
+// Every term is an explicit fma, so each kernel that uses it rounds alike.
+template <typename C>
+struct Post {
+  C ux, uy, fx, fy, omf, omg, Kf, Af, Bf, kf3, kf9, Kg, Ag, Bg, kc;
+
+  __device__ __forceinline__ void init(const Model &m, double rho, double E, C jx, C jy, C dr,
+                                       C dE, double Fx, double Fy, int treatment) {
+    const C rs = (C)rho, Es = (C)E;
+    const C ir = C(1) / rs;
+    fx = (C)Fx;
+    fy = (C)Fy;
+    ux = fma(C(0.5), fx, jx) * ir;
+    uy = fma(C(0.5), fy, jy) * ir;
+    const C uu = fma(ux, ux, uy * uy);
+    const C uF = fma(ux, fx, uy * fy);
+    const C itf = (C)m.inv_tau_f, itg = (C)m.inv_tau_g, kf = (C)m.kf;
+    omf = C(1) - itf;
+    omg = C(1) - itg;
+    const C tf = itf * rs, tg = itg * Es;
+    Af = C(3) * tf;
+    Bf = C(4.5) * tf;
+    kf3 = C(3) * kf;
+    kf9 = C(9) * kf;
+    Kf = fma(-kf3, uF, fma(C(-1.5) * tf, uu, itf * dr));
+    Ag = C(3) * tg;
+    Bg = C(4.5) * tg;
+    Kg = fma(C(-1.5) * tg, uu, itg * dE);
+    kc = treatment == 1 ? (C)m.kg * (C(3) * Es * ir) : C(0);
+  }
+
+  // the two brackets of direction i
+  __device__ __forceinline__ void bracket(int i, C &tf, C &tg) const {
+    if (i == 0) {
+      tf = Kf;
+      tg = Kg;
+      return;
+    }
+    const C sx = Q9::ex[i] > 0 ? ux : -ux, sy = Q9::ey[i] > 0 ? uy : -uy;
+    const C gx = Q9::ex[i] > 0 ? fx : -fx, gy = Q9::ey[i] > 0 ? fy : -fy;
+    const C eu = Q9::ex[i] == 0 ? sy : (Q9::ey[i] == 0 ? sx : sx + sy);
+    const C eF = Q9::ex[i] == 0 ? gy : (Q9::ey[i] == 0 ? gx : gx + gy);
+    tf = fma(kf3, eF, fma(eu, fma(kf9, eF, fma(Bf, eu, Af)), Kf));
+    tg = fma(kc, eF, fma(eu, fma(Bg, eu, Ag), Kg));
+  }
+
+  // values relative to the node's own reference
+  __device__ __forceinline__ void raw(int i, C fin, C gin, C &fs, C &gs) const {
+    C tf, tg;
+    bracket(i, tf, tg);
+    fs = fma(wgt<C>(i), tf, omf * fin);
+    gs = fma(wgt<C>(i), tg, omg * gin);
+  }
+
+  // values relative to a reference lower by dd (the node they land in);
+  // cvTr converts a density reference to the energy reference
+  __device__ __forceinline__ void shifted(int i, C fin, C gin, C dd, C cvTr, C &fo, C &go) const {
+    C tf, tg;
+    bracket(i, tf, tg);
+    fo = fma(wgt<C>(i), tf + dd, omf * fin);
+    go = fma(wgt<C>(i), fma(dd, cvTr, tg), omg * gin);
+  }
 };
 
 template <int BX, typename S>
@@ -301,17 +380,11 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
 
     // collision, Eq. (1) with the forcing term and Eq. (7)/(24), in C, on
     // deviations from the node's own reference
-    const C rs = (C)mm.rho;
-    const C ir = C(1) / rs;
-    const C fx = (C)Fx, fy = (C)Fy;
-    const C ux = (mm.jx + C(0.5) * fx) * ir;
-    const C uy = (mm.jy + C(0.5) * fy) * ir;
+    Post<C> P;
+    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    const C rs = (C)mm.rho, Es = (C)mm.E;
+    const C ux = P.ux, uy = P.uy;
     const C uu = ux * ux + uy * uy;
-    const C uF = ux * fx + uy * fy;
-    const C Es = (C)mm.E;
-    const C dr = mm.sf, dE = mm.sg;
-    const C itf = (C)m.inv_tau_f, itg = (C)m.inv_tau_g, kf = (C)m.kf;
-    const C kgc = treatment == 1 ? (C)m.kg * (C(3) * Es * ir) : C(0);
     const float rb_old = ST == ST_F32_LOCAL ? d.rb : 0.0f;
     const float *rn_m = L.rbn[(r - 1) & 3];
     const float *rn_0 = L.rbn[r & 3];
@@ -330,28 +403,12 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     constexpr int kx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ky[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     constexpr int ko[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    // post-collision values of direction i, relative to the own reference
-    auto post = [&](int i, C &fs, C &gs) {
-      const int exi = kx[i], eyi = ky[i];
-      const C eu = C(exi) * ux + C(eyi) * uy;
-      const C eF = C(exi) * fx + C(eyi) * fy;
-      const C X = C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu;
-      const C wi = wgt<C>(i);
-      const C feq = wi * (dr + rs * X);
-      const C Fi = kf * wi * (C(3) * (eF - uF) + C(9) * eu * eF);
+    // post-collision values of direction i, shifted (ST_F32_LOCAL) to the
+    // reference of the node with reference rd they land in
+    auto post_to = [&](int i, float rd, C &fs, C &gs) {
       const C fin = (C)d.v[i], gin = (C)d.v[9 + i];
-      fs = fin - (fin - feq) * itf + Fi;
-      const C geq = wi * (dE + Es * X);
-      gs = gin - (gin - geq) * itg + wi * kgc * eF;
-    };
-    // shift to the reference of the node the value lands in (ST_F32_LOCAL)
-    auto to_dest_ref = [&](int i, C &fs, C &gs) {
-      if (ST == ST_F32_LOCAL) {
-        const float *rr = ky[i] > 0 ? rn_p : (ky[i] < 0 ? rn_m : rn_0);
-        const C sh = wgt<C>(i) * (C)(rb_old - rr[c + kx[i]]);
-        fs += sh;
-        gs += sh * cvTr;
-      }
+      if (ST == ST_F32_LOCAL) P.shifted(i, fin, gin, (C)(rb_old - rd), cvTr, fs, gs);
+      else P.raw(i, fin, gin, fs, gs);
     };
     // Every lane issues the same 18 stores whatever its case, so the next
     // row's loads never wait for a store that sat in a masked branch; a lane
@@ -363,8 +420,8 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         C fs, gs;
-        post(i, fs, gs);
-        to_dest_ref(i, fs, gs);
+        const float *rr = ky[i] > 0 ? rn_p : (ky[i] < 0 ? rn_m : rn_0);
+        post_to(i, ST == ST_F32_LOCAL ? rr[c + kx[i]] : 0.0f, fs, gs);
         const int col = kx[i] > 0 ? xr : (kx[i] < 0 ? xl : x);
         const int row = ky[i] > 0 ? rU : (ky[i] < 0 ? rD : r);
         const unsigned cell = inner ? (unsigned)(row * pitch + col) : dummy;
@@ -374,20 +431,21 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        C fs, gs;
-        post(i, fs, gs);
         const int exi = kx[i], eyi = ky[i];
         const int col = exi > 0 ? xr : (exi < 0 ? xl : x);
         const int row = eyi > 0 ? rU : (eyi < 0 ? rD : r);
         const bool stays = col >= 0 && row >= 0;
         const C wi = wgt<C>(i);
-        // reference of the node the value lands in (ST_F32_LOCAL)
-        C sh = C(0);
+        // values in the reference of the node they land in (ST_F32_LOCAL),
+        // and relative to the own reference (wall formulas)
+        float rd = 0.0f;
         if (ST == ST_F32_LOCAL) {
           const float *rr = eyi > 0 ? rn_p : (eyi < 0 ? rn_m : rn_0);
-          const float rd = stays ? rr[c + exi] : rn_0[c];
-          sh = wi * (C)(rb_old - rd);
+          rd = stays ? rr[c + exi] : rn_0[c];
         }
+        C fo, go, fs, gs;
+        post_to(i, rd, fo, go);
+        P.raw(i, (C)d.v[i], (C)d.v[9 + i], fs, gs);
         // halfway bounce-back into the same node; the y wall wins at corners;
         // Dirichlet walls anti-bounce-back with the wall value rho cv T_w
         const bool hy = row < 0;
@@ -402,8 +460,8 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
                              : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
                                                     : (double)rn_0[c] * m.cvT_ref);
         const C g_abb = -gs + wi * (C)(2.0 * mm.rho * wE - refE - refEn);
-        C g_out = (stays || th != 0) ? gs + sh * cvTr : g_abb;
-        C f_out = fs + sh;
+        C g_out = (stays || th != 0) ? go : g_abb;
+        C f_out = fo;
         if (MODE == MODE_STEP_OPEN && m.wall_x == 2 && !stays && !hy) {
           const double refF = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rb_old);
           const double refFn = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)rn_0[c]);
@@ -417,7 +475,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
             // inlet: bounce-back carrying the inlet momentum; Dirichlet g
             // with the inlet equilibrium's even part
             const C eui = C(exi) * (C)m.u_in;
-            f_out = fs + sh - C(6) * wi * rs * eui;
+            f_out = fo - C(6) * wi * rs * eui;
             if (th == 0)
               g_out = -gs + wi * (C)(2.0 * mm.rho * wE * (1.0 + 3.0 * m.u_in * m.u_in) - refE - refEn);
           }
@@ -544,6 +602,344 @@ __global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__
   MomentsOut mo{};
   tile<ST, BX, MODE_STEP, PF>(m, src, dst, t.strip, y0, y1, t.dir, 0, treatment, bt.clamp[t.lattice],
                               mo, L, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch (temporal blocking along the band).
+//
+// On lattices periodic in x, with FP32 storage and the force of Eq. (2)
+// alone, one launch advances the state by two steps and the distributions
+// of the intermediate time level never reach HBM, which halves the HBM
+// traffic per step.  A block of BX lanes covers BX consecutive columns; the
+// inner BX - 6 lanes own a strip, and three halo columns per side supply
+// psi of the first step, the first step's pushes into the owned columns'
+// neighbours and psi of the second step.  At iteration j the block
+//   - takes the moments and psi of the first step on row j       (ring psi1),
+//   - takes the moments and psi of the second step on row j - 3, whose
+//     first-step distributions became complete with the pushes of row j - 2
+//     (ring psi2; the distributions are kept in registers),
+//   - collides row j - 1 (first step) and pushes the results into an LDS
+//     ring of three rows,
+//   - loads row j + 1,
+//   - collides row j - 4 (second step) and pushes the results to HBM with
+//     the same stores as the one-step kernel.
+// Rows are counted from three rows below the band (j = 0) to three rows
+// above it; at y walls rows outside the lattice are not collided and the
+// second step's psi ghost rows mirror the wall rows, as in the one-step
+// kernel.  The arithmetic of each step is the one-step kernel's, on the
+// same stored (FP32) values, so two one-step launches and one two-step
+// launch give the same result up to the compiler's contraction choices.
+
+template <int BX>
+struct PairLds {
+  float f1[3][18][BX];  // distributions after the first step, stored form
+  double psi1[4][BX];
+  double psi2[4][BX];
+  float rb1[4][BX];     // per-node references after the first step (ST_F32_LOCAL)
+  float rb2[4][BX];     // and after the second
+};
+
+template <int ST, int BX>
+__global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__restrict__ src_v,
+                                             void *__restrict__ dst_v, int treatment,
+                                             unsigned long long *clamp_counter) {
+  using S = float;
+  using C = typename Prec<ST>::C;
+  __shared__ PairLds<BX> L;
+  const int tid = tile_of_block(t);
+  if (tid >= t.strips * t.bands) return;
+  const int strip = tid % t.strips;
+  const int band = tid / t.strips;
+  const int y0 = band * t.rows;
+  const int n = min(y0 + t.rows, m.ny) - y0;
+  const Bufs sb = make_bufs<S>(src_v, m);
+  const Bufs db = make_bufs<S>(dst_v, m);
+  const unsigned pb = (unsigned)(m.plane * (long long)sizeof(S));
+  constexpr unsigned sz = sizeof(S);
+
+  const int lane = threadIdx.x;
+  const int nx = m.nx, ny = m.ny, pitch = m.pitch;
+  const int x0 = strip * (BX - 6);
+  const int nint = min(BX - 6, nx - x0);
+  const bool active = lane < nint + 6;
+  const bool own = lane >= 3 && lane < nint + 3;  // owns its column
+  // a wave with no active lane (the last strip of a lattice) only keeps
+  // the block's barriers
+  const bool wave_live = (lane & ~63) < nint + 6;
+  auto wrap = [](int v, int len) {
+    const int r = v % len;
+    return r < 0 ? r + len : r;
+  };
+  const int x = active ? wrap(x0 - 3 + lane, nx) : 0;
+  const int xl = wrap(x - 1, nx), xr = wrap(x + 1, nx);
+  const int c = (lane >= 1 && lane <= BX - 2) ? lane : 1;  // stencil centre in a ring row
+
+  auto vrow = [&](int j) { return y0 - 3 + j; };
+  auto inside = [&](int v) { return !m.wall_y || (v >= 0 && v < ny); };
+  auto prow = [&](int v) { return m.wall_y ? min(max(v, 0), ny - 1) : wrap(v, ny); };
+
+  long long clamps = 0;
+  const C cvTr = (C)m.cvT_ref;
+
+  auto load_row = [&](int j, Row<S> &d) {
+    const int r = prow(vrow(j));
+    const unsigned off = (unsigned)(r * pitch + x) * sz;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d.v[q] = bld(sb.f, off, (unsigned)q * pb, (S *)nullptr);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d.v[9 + q] = bld(sb.g, off, (unsigned)q * pb, (S *)nullptr);
+    if (ST == ST_F32_LOCAL) {
+      const unsigned rc = (unsigned)(r * m.rpitch + x);
+      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(sb.ref, (int)(rc * 2u), 0, 0);
+      d.rb = (float)__builtin_bit_cast(_Float16, h);
+    }
+  };
+
+  auto load_f1 = [&](int j, Row<S> &d) {
+    const float *f = &L.f1[j % 3][0][0];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) d.v[q] = f[q * BX + lane];
+    if (ST == ST_F32_LOCAL) d.rb = L.rb1[j & 3][lane];
+  };
+
+  // rho, j, E of the stored values; the deviation sums in the one-step
+  // kernel's precision (FP32 for per-node references, else FP64)
+  auto moments = [&](const Row<S> &d, Mom<C> &mm) {
+    double a, b;
+    if (ST == ST_F32_LOCAL) {
+      float fa = d.v[0];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) fa += d.v[q];
+      float fb = d.v[9];
+#pragma unroll
+      for (int q = 10; q < 18; ++q) fb += d.v[q];
+      a = (double)fa;
+      b = (double)fb;
+    } else {
+      a = (double)d.v[0];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) a += (double)d.v[q];
+      b = (double)d.v[9];
+#pragma unroll
+      for (int q = 10; q < 18; ++q) b += (double)d.v[q];
+    }
+    const C v1 = (C)d.v[1], v2 = (C)d.v[2], v3 = (C)d.v[3], v4 = (C)d.v[4], v5 = (C)d.v[5],
+            v6 = (C)d.v[6], v7 = (C)d.v[7], v8 = (C)d.v[8];
+    mm.jx = ((v1 - v3) + (v5 - v6)) + (v8 - v7);
+    mm.jy = ((v2 - v4) + (v5 + v6)) - (v7 + v8);
+    const double ref = ST == ST_F32_GLOBAL ? m.rho_ref : (double)d.rb;
+    mm.sf = (C)a;
+    mm.sg = (C)b;
+    mm.rho = ref + a;
+    mm.E = ref * m.cvT_ref + b;
+  };
+
+  // Eq. (2) force (beta = 1) from a psi ring, plus the body force
+  auto force = [&](const double *pm, const double *p0, const double *pp, double rho, double &Fx,
+                   double &Fy) {
+    Fx = 0.0;
+    Fy = 0.0;
+    if (m.sc_on) {
+      const double sx = (p0[c + 1] - p0[c - 1]) * (1.0 / 3.0) +
+                        ((pp[c + 1] - pp[c - 1]) + (pm[c + 1] - pm[c - 1])) * (1.0 / 12.0);
+      const double sy = (pp[c] - pm[c]) * (1.0 / 3.0) +
+                        ((pp[c + 1] + pp[c - 1]) - (pm[c + 1] + pm[c - 1])) * (1.0 / 12.0);
+      const double gb = -m.G * m.beta * p0[c];
+      Fx = gb * sx;
+      Fy = gb * sy;
+    }
+    Fx += rho * m.gx;
+    Fy += rho * m.gy;
+  };
+
+  // post-collision values of direction i in the reference rd of the node
+  // they land in (ST_F32_LOCAL), and relative to the own reference
+  auto post_to = [&](const Post<C> &P, const Row<S> &d, int i, float rd, C &fo, C &go) {
+    const C fin = (C)d.v[i], gin = (C)d.v[9 + i];
+    if (ST == ST_F32_LOCAL) P.shifted(i, fin, gin, (C)(d.rb - rd), cvTr, fo, go);
+    else P.raw(i, fin, gin, fo, go);
+  };
+
+  // anti-bounce-back value of g at a Dirichlet y wall, from the value gs
+  // relative to the own reference before the step (rb_old) and the own
+  // reference after it (rb_new)
+  auto g_wall = [&](int i, C gs, double rho, float rb_old, float rb_new) {
+    const double wE = Q9::ey[i] < 0 ? m.wall_E[2] : m.wall_E[3];
+    const double refE = ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_old * m.cvT_ref;
+    const double refEn = ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_new * m.cvT_ref;
+    return -gs + wgt<C>(i) * (C)(2.0 * rho * wE - refE - refEn);
+  };
+
+  auto psi_first = [&](int j, const Row<S> &d, Mom<C> &mm) {
+    moments(d, mm);
+    double psi, s;
+    int cl;
+    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    L.psi1[j & 3][lane] = psi;
+    if (ST == ST_F32_LOCAL) L.rb1[j & 3][lane] = ref_of(mm.rho);
+    const int v = vrow(j);
+    if (own && v >= y0 && v < y0 + n) clamps += cl;
+  };
+
+  auto psi_second = [&](int j, Row<S> &d, Mom<C> &mm) {
+    load_f1(j, d);
+    moments(d, mm);
+    double psi, s;
+    int cl;
+    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    const int v = vrow(j);
+    L.psi2[j & 3][lane] = psi;
+    if (ST == ST_F32_LOCAL) L.rb2[j & 3][lane] = ref_of(mm.rho);
+    if (m.wall_y && v == 0) L.psi2[(j - 1) & 3][lane] = psi;  // mirror ghost rows
+    if (m.wall_y && v == ny - 1) L.psi2[(j + 1) & 3][lane] = psi;
+    if (own && v >= y0 && v < y0 + n) clamps += cl;
+  };
+
+  // first step of row j: pushes into the LDS ring (bounce-back at y walls)
+  auto collide_first = [&](int j, const Row<S> &d, const Mom<C> &mm) {
+    const int v = vrow(j);
+    double Fx, Fy;
+    force(L.psi1[(j - 1) & 3], L.psi1[j & 3], L.psi1[(j + 1) & 3], mm.rho, Fx, Fy);
+    Post<C> P;
+    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    const float *rn_m = L.rb1[(j - 1) & 3];
+    const float *rn_0 = L.rb1[j & 3];
+    const float *rn_p = L.rb1[(j + 1) & 3];
+    const bool wd = m.wall_y && v == 0, wu = m.wall_y && v == ny - 1;
+    float *fm = &L.f1[(j + 2) % 3][0][0];
+    float *f0 = &L.f1[j % 3][0][0];
+    float *fp = &L.f1[(j + 1) % 3][0][0];
+    // every lane stores: the lanes that do not collide in this step (the
+    // two edges of the block) write inside the ring row, into entries that
+    // no owned column reads
+    const int tl = lane > 0 ? lane - 1 : 0, tr = lane < BX - 1 ? lane + 1 : BX - 1;
+    auto push = [&](int i, C fo, C go) {
+      const int exi = Q9::ex[i], eyi = Q9::ey[i];
+      float *f = eyi > 0 ? fp : (eyi < 0 ? fm : f0);
+      const int to = exi > 0 ? tr : (exi < 0 ? tl : lane);
+      f[i * BX + to] = (S)fo;
+      f[(9 + i) * BX + to] = (S)go;
+    };
+    {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int exi = Q9::ex[i], eyi = Q9::ey[i];
+        const bool hy = (eyi < 0 && wd) || (eyi > 0 && wu);
+        float rd = 0.0f;
+        if (ST == ST_F32_LOCAL) {
+          const float *rr = eyi > 0 ? rn_p : (eyi < 0 ? rn_m : rn_0);
+          rd = hy ? rn_0[c] : rr[c + exi];
+        }
+        C fo, go;
+        post_to(P, d, i, rd, fo, go);
+        if (!hy) {
+          push(i, fo, go);
+        } else {
+          C fs, gs;
+          P.raw(i, (C)d.v[i], (C)d.v[9 + i], fs, gs);
+          const int th = eyi < 0 ? m.thermal[2] : m.thermal[3];
+          const C g_out = th != 0 ? go : g_wall(i, gs, mm.rho, d.rb, rd);
+          f0[Q9::opp[i] * BX + lane] = (S)fo;
+          f0[(9 + Q9::opp[i]) * BX + lane] = (S)g_out;
+        }
+      }
+    }
+  };
+
+  // second step of row j: pushes to HBM; every lane issues the same stores
+  // (lanes that own no column write into the pad past the plane)
+  auto collide_second = [&](int j, const Row<S> &d, const Mom<C> &mm) {
+    const int r = vrow(j);
+    double Fx, Fy;
+    force(L.psi2[(j - 1) & 3], L.psi2[j & 3], L.psi2[(j + 1) & 3], mm.rho, Fx, Fy);
+    Post<C> P;
+    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    const float *rn_m = L.rb2[(j - 1) & 3];
+    const float *rn_0 = L.rb2[j & 3];
+    const float *rn_p = L.rb2[(j + 1) & 3];
+    const int rD = r > 0 ? r - 1 : (m.wall_y ? -1 : ny - 1);
+    const int rU = r < ny - 1 ? r + 1 : (m.wall_y ? -1 : 0);
+    const unsigned dummy = (unsigned)(ny * pitch + lane);
+    const unsigned self = own ? (unsigned)(r * pitch + x) : dummy;
+    if (ST == ST_F32_LOCAL)
+      __builtin_amdgcn_raw_buffer_store_b16(
+          __builtin_bit_cast(unsigned short, (_Float16)rn_0[c]), db.ref,
+          (int)((unsigned)(own ? r * m.rpitch + x : ny * m.rpitch + lane) * 2u), 0, 0);
+    if (rD >= 0 && rU >= 0) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int col = Q9::ex[i] > 0 ? xr : (Q9::ex[i] < 0 ? xl : x);
+        const int row = Q9::ey[i] > 0 ? rU : (Q9::ey[i] < 0 ? rD : r);
+        float rd = 0.0f;
+        if (ST == ST_F32_LOCAL) {
+          const float *rr = Q9::ey[i] > 0 ? rn_p : (Q9::ey[i] < 0 ? rn_m : rn_0);
+          rd = rr[c + Q9::ex[i]];
+        }
+        C f_out, g_out;
+        post_to(P, d, i, rd, f_out, g_out);
+        const unsigned cell = own ? (unsigned)(row * pitch + col) : dummy;
+        bst(db.f, cell * sz + (unsigned)i * pb, 0u, (S)f_out);
+        bst(db.g, cell * sz + (unsigned)i * pb, 0u, (S)g_out);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int exi = Q9::ex[i], eyi = Q9::ey[i];
+        const int col = exi > 0 ? xr : (exi < 0 ? xl : x);
+        const int row = eyi > 0 ? rU : (eyi < 0 ? rD : r);
+        const bool stays = row >= 0;
+        float rd = 0.0f;
+        if (ST == ST_F32_LOCAL) {
+          const float *rr = eyi > 0 ? rn_p : (eyi < 0 ? rn_m : rn_0);
+          rd = stays ? rr[c + exi] : rn_0[c];
+        }
+        C f_out, g_out;
+        post_to(P, d, i, rd, f_out, g_out);
+        unsigned q = (unsigned)i, cell = own ? (unsigned)(row * pitch + col) : dummy;
+        if (!stays) {
+          const int th = eyi < 0 ? m.thermal[2] : m.thermal[3];
+          if (th == 0) {
+            C fs, gs;
+            P.raw(i, (C)d.v[i], (C)d.v[9 + i], fs, gs);
+            g_out = g_wall(i, gs, mm.rho, d.rb, rd);
+          }
+          q = (unsigned)Q9::opp[i];
+          cell = self;
+        }
+        bst(db.f, cell * sz + q * pb, 0u, (S)f_out);
+        bst(db.g, cell * sz + q * pb, 0u, (S)g_out);
+      }
+    }
+  };
+
+  // the pipeline; register buffers alternate with the parity of j
+  Row<S> R[2], F[2];
+  Mom<C> M[2], M2[2];
+  const int J = n + 7;
+  if (wave_live) load_row(0, R[0]);
+  for (int j0 = 0; j0 < J; j0 += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = j0 + u;
+      if (j < J) {
+        if (wave_live) {
+          if (j < n + 6) psi_first(j, R[u], M[u]);
+          const int j2 = j - 3;
+          if (j2 >= 2 && j2 < n + 4 && inside(vrow(j2))) psi_second(j2, F[u ^ 1], M2[u ^ 1]);
+        }
+        __syncthreads();
+        if (wave_live) {
+          const int j1 = j - 1;
+          if (j1 >= 1 && j1 < n + 5 && inside(vrow(j1))) collide_first(j1, R[u ^ 1], M[u ^ 1]);
+          if (j + 1 < n + 6) load_row(j + 1, R[u ^ 1]);
+          const int j4 = j - 4;
+          if (j4 >= 3 && j4 < n + 3) collide_second(j4, F[u], M2[u]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (clamps && clamp_counter) atomicAdd(clamp_counter, (unsigned long long)clamps);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,9 +1233,25 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
     if (t.pf >= 2) return launch_tile_st<MODE_STEP_OPEN, 2>(m, t, st, src, dst, treatment, cc, mo, s);
     return launch_tile_st<MODE_STEP_OPEN, 1>(m, t, st, src, dst, treatment, cc, mo, s);
   }
-  if (t.pf >= 3) return launch_tile_st<MODE_STEP, 3>(m, t, st, src, dst, treatment, cc, mo, s);
-  if (t.pf == 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
+  if (t.pf >= 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
   return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+}
+
+hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                       int treatment, unsigned long long *cc, hipStream_t s) {
+  const unsigned grid = tile_grid(t);
+  if (t.bx != 256 || m.wall_x != 0 || !(m.beta_one || !m.sc_on)) return hipErrorInvalidValue;
+  switch (st) {
+    case ST_F32_GLOBAL:
+      hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
+      break;
+    case ST_F32_LOCAL:
+      hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_moments(const Model &m, const Tiling &t, int st, const void *src,
@@ -933,8 +1345,7 @@ hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char 
   } while (0)
 #define LBM_PF(ST_)                      \
   do {                                   \
-    if (pf >= 3) LBM_BX(ST_, 3);         \
-    else if (pf == 2) LBM_BX(ST_, 2);    \
+    if (pf >= 2) LBM_BX(ST_, 2);         \
     else LBM_BX(ST_, 1);                 \
   } while (0)
   if (st == ST_F64) {

@@ -88,6 +88,8 @@ def lib():
             "lbm_load": [vp, ctypes.c_char_p],
             "lbm_set_tiling": [vp, i, i],
             "lbm_get_tiling": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
+            "lbm_set_step_pairing": [vp, i, i],
+            "lbm_get_step_pairing": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
             "lbm_destroy": [vp],
             "lbm_copy_probe": [vp, vp, sz, vp],
             "lbm_batch_workspace_bytes": [i, P, ctypes.POINTER(sz)],
@@ -242,6 +244,15 @@ class _HandleOps:
         a, b = ctypes.c_int(), ctypes.c_int()
         _chk("lbm_get_tiling", lib().lbm_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def set_step_pairing(self, on, rows=0):
+        _chk("lbm_set_step_pairing", lib().lbm_set_step_pairing(self._h, int(bool(on)), int(rows)))
+
+    def get_step_pairing(self):
+        """(pairing used by step(), rows per block of the two-step kernel)"""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _chk("lbm_get_step_pairing", lib().lbm_get_step_pairing(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), b.value
 
 
 class Lattice(_HandleOps):

@@ -23,12 +23,14 @@ def say(*a):
 
 
 def gpu_run(cfg, rho, T, steps, treatment, precision="fp64", ux=None, uy=None, tiling=None,
-            chunks=None):
+            chunks=None, pair=None):
     from paper_1405_2232_amd.lbm import Lattice
     g = Lattice(cfg, precision)
     g.init_fields(rho, T, ux, uy)
     if tiling is not None:
         g.set_tiling(*tiling)
+    if pair is not None:
+        g.set_step_pairing(pair)
     for n in (chunks or [steps]):
         if n > 0:
             g.step(n, treatment)

@@ -1,0 +1,133 @@
+"""Two steps per launch (temporal blocking) against one-step launches and
+against the FP64 oracle.
+
+The two-step kernel runs the one-step kernel's arithmetic on the same
+stored FP32 values, so pairing steps must leave the state bit for bit
+unchanged, and the result must meet the FP32 parity bar against the
+oracle.  Cases span several strips and bands with ragged tails, y walls
+(Dirichlet and adiabatic), gravity, odd step counts (a one-step launch at
+the end), periodic checks falling between pairs, and lattices narrower or
+shorter than one tile."""
+import numpy as np
+import pytest
+
+from gpu_util import compare_fp32dev, need_gpu, oracle_run, say
+from oracle import CORRECTED, PLAIN
+from paper_1405_2232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _run(p, rho, T, steps, tr, precision, pair, rows=0, check=0, chunks=None):
+    from paper_1405_2232_amd.lbm import Lattice
+    g = Lattice(p, precision)
+    g.init_fields(rho, T)
+    g.set_step_pairing(pair, rows)
+    if check:
+        g.set_check_interval(check)
+    for n in (chunks or [steps]):
+        g.step(n, tr)
+    return g
+
+
+def _cases():
+    Tc = inputs.cs_tc()
+    out = []
+    p, rho, T = inputs.static_droplet()
+    out.append(("64x64 droplet", p, rho, T, 301, CORRECTED))
+    p, rho, T = inputs.static_droplet()
+    p["eos_fixed_T"] = True
+    out.append(("64x64 droplet plain fixed-T", p, rho, T, 300, PLAIN))
+    p, rho, T = inputs.static_droplet(nx=300, ny=70, radius=15, seed=11)
+    p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc, gy=-2e-5)
+    out.append(("300x70 walls+gravity", p, rho, T, 301, CORRECTED))
+    p, rho, T = inputs.static_droplet(nx=520, ny=33, radius=10, seed=13)
+    p.update(wall_y=True, thermal_bottom="adiabatic", thermal_top="dirichlet", T_top=0.9 * Tc,
+             gx=1e-5)
+    out.append(("520x33 adiabatic bottom", p, rho, T, 150, CORRECTED))
+    p, rho, T = inputs.static_droplet(nx=37, ny=23, radius=7, seed=12)
+    p["eos_fixed_T"] = True
+    out.append(("37x23 periodic plain", p, rho, T, 201, PLAIN))
+    p, rho, T = inputs.static_droplet(nx=1, ny=48, radius=10, seed=14)
+    out.append(("1x48", p, rho, T, 200, CORRECTED))
+    p, rho, T = inputs.static_droplet(nx=48, ny=1, radius=10, seed=15)
+    out.append(("48x1", p, rho, T, 200, CORRECTED))
+    p, rho, T = inputs.static_droplet(nx=20, ny=5, radius=3, seed=17)
+    p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc)
+    out.append(("20x5 walls", p, rho, T, 99, CORRECTED))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32local", "fp32dev"])
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
+def test_pairs_equal_single_steps(case, precision):
+    name, p, rho, T, steps, tr = case
+    say("case pair", name, precision, steps)
+    a = _run(p, rho, T, steps, tr, precision, pair=False)
+    b = _run(p, rho, T, steps, tr, precision, pair=True)
+    assert b.get_step_pairing()[0]
+    sa, sb = a.get_state(), b.get_state()
+    d = float(np.max(np.abs(sa - sb)))
+    say("pair vs single max |d state|", name, precision, d)
+    assert np.array_equal(sa, sb), (name, d)
+    ta, tb = a.totals(), b.totals()
+    assert ta[5] == tb[5] and ta[6] == tb[6] == steps
+    if precision == "fp32local":
+        o = oracle_run(p, rho, T, steps, tr)
+        compare_fp32dev(b.moments(), o.moments(), what=("pair", name))
+
+
+def test_pair_rows_invariance():
+    Tc = inputs.cs_tc()
+    p, rho, T = inputs.static_droplet(nx=150, ny=90, radius=20, seed=21)
+    p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc)
+    ref = None
+    for rows in (8, 1, 3, 16, 90):
+        say("case pair rows", rows)
+        s = _run(p, rho, T, 60, CORRECTED, "fp32local", pair=True, rows=rows).get_state()
+        if ref is None:
+            ref = s
+        else:
+            assert np.array_equal(s, ref), rows
+
+
+def test_pair_with_checks_and_chunks():
+    """Periodic checks between pairs and odd chunk lengths keep the state
+    and the step count of one-step launches."""
+    p, rho, T = inputs.static_droplet(seed=5)
+    a = _run(p, rho, T, 0, CORRECTED, "fp32local", pair=False, chunks=[157])
+    b = _run(p, rho, T, 0, CORRECTED, "fp32local", pair=True, check=7, chunks=[3, 50, 1, 103])
+    assert np.array_equal(a.get_state(), b.get_state())
+    assert b.totals()[6] == 157
+
+
+def test_pair_clamp_count():
+    """The plain treatment with the EOS at the local T leaves the real-psi
+    domain after a few tens of steps: the clamp count (first and second step
+    of each pair) equals the one-step count."""
+    p, rho, T = inputs.static_droplet()
+    a = _run(p, rho, T, 80, PLAIN, "fp32local", pair=False)
+    b = _run(p, rho, T, 80, PLAIN, "fp32local", pair=True)
+    ca, cb = a.totals()[5], b.totals()[5]
+    say("clamps single", ca, "pair", cb)
+    assert ca > 0 and ca == cb
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_pair_eligibility():
+    from paper_1405_2232_amd.lbm import Lattice
+    p, rho, T = inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)
+    for prec, extra, want in (("fp32local", {}, True), ("fp32dev", {}, True), ("fp64", {}, False),
+                              ("fp32local", {"wall_x": True}, False),
+                              ("fp32local", {"beta": 0.5}, False),
+                              ("fp32local", {"G": 0.0, "beta": 0.5}, True)):
+        g = Lattice(dict(p, **extra), prec)
+        g.init_fields(rho, T)
+        assert g.get_step_pairing()[0] == want, (prec, extra)
+        g.set_step_pairing(False)
+        assert not g.get_step_pairing()[0]

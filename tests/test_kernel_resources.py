@@ -2,7 +2,8 @@
 compiles for gfx950): no step or batch kernel may use scratch memory (a
 spilled row buffer costs 2.5x in throughput) or drop below two waves per
 SIMD.  The open-channel variants (mode 2, small lattices) may spill a few
-bytes but no row buffer (at most 64 bytes per lane)."""
+bytes but no row buffer (at most 64 bytes per lane); so may the two-step
+kernel, whose frame reserves a few bytes for spilled scalars."""
 import os
 import re
 import subprocess
@@ -29,11 +30,11 @@ def test_step_kernels_use_no_scratch():
         if m:
             cur = m.group(1)
             continue
-        if cur and ("k_tile" in cur or "k_batch" in cur):
+        if cur and ("k_tile" in cur or "k_batch" in cur or "k_pair" in cur):
             m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
             if m:
                 seen += 1
-                limit = 64 if re.search(r"k_tileILi\dELi\d+ELi2E", cur) else 0
+                limit = 64 if (re.search(r"k_tileILi\dELi\d+ELi2E", cur) or "k_pair" in cur) else 0
                 if int(m.group(1)) > limit:
                     bad.append((cur, "scratch", int(m.group(1))))
             m = re.search(r"Occupancy \[waves/SIMD\]: (\d+)", line)
