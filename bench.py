@@ -113,7 +113,7 @@ def traffic_summary(args):
     written), then the per-launch mean over the step kernel's dispatches is
     written with the hash of the kernel sources it was taken on."""
     import re
-    step = re.compile(r"lbmdev::k_tile<(\d+), (\d+), 0, (\d+)>")
+    step = re.compile(r"lbmdev::k_tile<(\d+), (\d+), 0, (\d+)>|lbmdev::k_pair<(\d+), (\d+)>")
     out = {"precision": args.precision, "nx": args.nx, "ny": args.ny,
            "layout": "row-interleaved", "kernel_hash": kernel_hash()}
     copy_kib = float(1 << 20)
@@ -131,12 +131,14 @@ def traffic_summary(args):
         scale = copy_kib / (sum(copies) / len(copies))
         raw = sum(vals) / len(vals)
         out["kernel"] = name
+        out["steps_per_launch"] = 2 if "k_pair" in name else 1
         out[key + "_kib_raw"] = round(raw, 1)
         out[key + "_scale"] = round(scale, 4)
         out[key + "_bytes"] = int(raw * scale * 1024)
         out[key + "_launches"] = len(vals)
     out["bytes_per_launch"] = out["fetch_bytes"] + out["write_bytes"]
     out["bytes_per_node"] = round(out["bytes_per_launch"] / (args.nx * args.ny), 1)
+    out["bytes_per_node_step"] = round(out["bytes_per_node"] / out["steps_per_launch"], 1)
     with open(TRAFFIC_FILE, "w") as fp:
         json.dump(out, fp, indent=1)
         fp.write("\n")
@@ -314,18 +316,23 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     mlups = cells * args.steps / wall / 1e6
 
-    # step kernel alone, HIP events on the launch stream
+    # step kernel alone, HIP events on the launch stream; with step pairing
+    # one launch advances two steps (an even step count: every launch pairs)
     g.set_check_interval(0)
-    k_steps = min(500, max(50, args.steps // 4))
+    paired = g.get_step_pairing()[0]
+    per_launch = 2 if paired else 1
+    k_steps = 2 * (min(500, max(50, args.steps // 4)) // 2)
     kernel_ms = timed_steps(g, k_steps, treatment, torch)
-    achieved = ALG_BYTES[args.precision] * cells / (kernel_ms * 1e-3) / 1e9
+    launch_ms = kernel_ms * per_launch
+    achieved = ALG_BYTES[args.precision] * cells * per_launch / (launch_ms * 1e-3) / 1e9
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fp:
             tr = json.load(fp)
         if tr.get("kernel_hash") == kernel_hash() and tr.get("precision") == args.precision \
-                and tr.get("nx") == args.nx and tr.get("ny") == args.ny:
+                and tr.get("nx") == args.nx and tr.get("ny") == args.ny \
+                and tr.get("steps_per_launch", 1) == per_launch:
             traffic = tr.get("bytes_per_launch")
 
     copy_ms, copy_gbs = copy_rate(1 << 30)
@@ -366,8 +373,14 @@ def main():
                    "walls": "0.80 Tc / 0.90 Tc", "check_every": 100},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel_ms": round(kernel_ms, 5),
+                     "traffic": traffic,
+                     "kernel": "k_pair" if paired else "k_tile",
+                     "steps_per_launch": per_launch,
+                     "launch_ms": round(launch_ms, 5),
+                     "kernel_ms": round(kernel_ms, 5),
                      "bytes_per_node": ALG_BYTES[args.precision],
+                     "measured_GBs": (round(traffic / (launch_ms * 1e-3) / 1e9, 1)
+                                      if traffic else None),
                      "copy_GBs": round(copy_gbs, 1)},
         "by_precision": extra,
     }

@@ -201,7 +201,8 @@ int lbm_set_tiling(lbm_handle h, int bx, int rows);
  * stay on chip, which halves the HBM traffic per step.  The arithmetic of
  * each step is the one-step kernel's.  `on` = 0 makes every step a
  * one-step launch; `rows` (> 0) sets the rows per block of the two-step
- * kernel, 0 keeps the current value.  Default: on, 8 rows.  A step that
+ * kernel, 0 keeps the current value.  Default: on, with the rows chosen
+ * from the lattice size and the device's compute units.  A step that
  * ends at a periodic check is always a one-step launch.
  * lbm_get_step_pairing reports whether lbm_step will pair steps (`active`)
  * and the rows per block.  LBM_EINVAL for a NULL handle or rows < 0. */

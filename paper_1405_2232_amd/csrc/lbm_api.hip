@@ -43,13 +43,38 @@ Tiling default_tiling(int nx, int ny, int precision) {
   return t;
 }
 
-// Two-step tiling: 256 lanes, strips of 250 owned columns, bands of `rows`
-// rows (8 by default: each band recomputes the first step on four extra
-// rows, so short bands cost arithmetic and long ones cost blocks).
+// Compute units of the current device (256 on MI355X).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 256;
+  return cus;
+}
+
+// Two-step tiling.  Blocks of 128 lanes (122 owned columns) run four to a
+// CU (two waves per SIMD; the LDS rings take 40 KB per block).  A band of r
+// rows costs the block about 2 r + 4 row collisions (the first step also
+// runs on two rows beyond each band edge), and the blocks of a launch run
+// in ceil(blocks / slots) rounds; rows <= 0 picks the r in [6, 16] that
+// minimises rounds x (2 r + 4).
 Tiling pair_tiling(int nx, int ny, int rows) {
   Tiling t;
-  t.bx = 256;
+  const long long ebx = env_ll("LBM_PAIR_BX", 128);
+  t.bx = ebx == 64 ? 64 : (ebx == 256 ? 256 : 128);
   t.strips = (nx + t.bx - 7) / (t.bx - 6);
+  if (rows <= 0) {
+    const long long slots = (long long)device_cus() * (512 / t.bx);
+    long long best = -1;
+    for (int r = 6; r <= 16; ++r) {
+      const long long blocks = (long long)t.strips * ((ny + r - 1) / r);
+      const long long cost = ((blocks + slots - 1) / slots) * (2 * r + 4);
+      if (best < 0 || cost < best) {
+        best = cost;
+        rows = r;
+      }
+    }
+  }
   t.rows = rows < ny ? rows : ny;
   t.bands = (ny + t.rows - 1) / t.rows;
   t.xcd = (int)env_ll("LBM_XCD", 1);
@@ -305,7 +330,7 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->st = storage_of(p);
   h->t = default_tiling(p->nx, p->ny, p->precision);
   h->tm = h->t;
-  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 8) > 0 ? (int)env_ll("LBM_PAIR_ROWS", 8) : 8);
+  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0));
   h->pair_ok = h->st != lbmdev::ST_F64 && p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
   h->pair_on = env_ll("LBM_PAIR", 1) != 0;
   h->stream = (hipStream_t)hip_stream;

@@ -81,7 +81,7 @@ inline int strip_width(int bx) { return bx - 2; }
 hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *clamp_counter, hipStream_t s);
 // Two steps in one launch (FP32 storage, x periodic, beta = 1 or no
-// interaction force; bx 256, strips of bx - 6 owned columns): src holds time
+// interaction force; bx 64, 128 or 256, strips of bx - 6 owned columns): src holds time
 // t, dst receives time t + 2.
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *clamp_counter, hipStream_t s);

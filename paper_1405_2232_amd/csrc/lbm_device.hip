@@ -65,15 +65,16 @@ __device__ inline double pressure(const Model &m, double rho, double T) {
 }
 
 // psi^2 = 2 (p_EOS - rho c_s^2)/(G c^2); psi clamps to 0 outside the domain.
-__device__ inline void node_psi(const Model &m, double rho, double E, double &psi, double &s,
-                                int &clamped) {
+// ir = 1/rho
+__device__ inline void node_psi(const Model &m, double rho, double E, double ir, double &psi,
+                                double &s, int &clamped) {
   clamped = 0;
   if (!m.sc_on) {
     psi = 0.0;
     s = 0.0;
     return;
   }
-  const double T = m.eos_fixed_T ? m.T_eos : E * m.inv_cv / rho;
+  const double T = m.eos_fixed_T ? m.T_eos : E * m.inv_cv * ir;
   s = (pressure(m, rho, T) - rho * (1.0 / 3.0)) * m.two_over_G;
   if (s >= 0.0) {
     psi = sqrt(s);
@@ -136,7 +137,7 @@ struct Row {
 
 template <typename C>
 struct Mom {
-  double rho, E;
+  double rho, E, ir;  // ir = 1/rho
   C jx, jy;  // first moment of f
   C sf, sg;  // deviation sums (rho - ref, E - ref * cvT_ref)
 };
@@ -155,10 +156,12 @@ template <typename C>
 struct Post {
   C ux, uy, fx, fy, omf, omg, Kf, Af, Bf, kf3, kf9, Kg, Ag, Bg, kc;
 
-  __device__ __forceinline__ void init(const Model &m, double rho, double E, C jx, C jy, C dr,
-                                       C dE, double Fx, double Fy, int treatment) {
+  __device__ __forceinline__ void init(const Model &m, double rho, double E, double irho, C jx,
+                                       C jy, C dr, C dE, double Fx, double Fy, int treatment) {
     const C rs = (C)rho, Es = (C)E;
-    const C ir = C(1) / rs;
+    // FP64 arithmetic reuses 1/rho from the psi evaluation; FP32
+    // arithmetic divides in FP32
+    const C ir = sizeof(C) == sizeof(double) ? (C)irho : C(1) / rs;
     fx = (C)Fx;
     fy = (C)Fy;
     ux = fma(C(0.5), fx, jx) * ir;
@@ -305,9 +308,11 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     mm.sg = (C)sg;
     mm.rho = ref + sf;
     mm.E = ref * m.cvT_ref + sg;
+    // 1/rho is recomputed at the collision (same bits) rather than carried:
+    // two more live registers per row cost this kernel more than a division
     double psi, s;
     int cl;
-    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    node_psi(m, mm.rho, mm.E, 1.0 / mm.rho, psi, s, cl);
     L.psi[slot][lane] = psi;
     L.s[slot][lane] = s;
     if (ST == ST_F32_LOCAL) L.rbn[slot][lane] = ref_of(mm.rho);
@@ -381,7 +386,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     // collision, Eq. (1) with the forcing term and Eq. (7)/(24), in C, on
     // deviations from the node's own reference
     Post<C> P;
-    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    P.init(m, mm.rho, mm.E, 1.0 / mm.rho, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
     const C rs = (C)mm.rho, Es = (C)mm.E;
     const C ux = P.ux, uy = P.uy;
     const C uu = ux * ux + uy * uy;
@@ -732,6 +737,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     mm.sg = (C)b;
     mm.rho = ref + a;
     mm.E = ref * m.cvT_ref + b;
+    mm.ir = 1.0 / mm.rho;
   };
 
   // Eq. (2) force (beta = 1) from a psi ring, plus the body force
@@ -774,7 +780,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     moments(d, mm);
     double psi, s;
     int cl;
-    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    node_psi(m, mm.rho, mm.E, mm.ir, psi, s, cl);
     L.psi1[j & 3][lane] = psi;
     if (ST == ST_F32_LOCAL) L.rb1[j & 3][lane] = ref_of(mm.rho);
     const int v = vrow(j);
@@ -786,7 +792,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     moments(d, mm);
     double psi, s;
     int cl;
-    node_psi(m, mm.rho, mm.E, psi, s, cl);
+    node_psi(m, mm.rho, mm.E, mm.ir, psi, s, cl);
     const int v = vrow(j);
     L.psi2[j & 3][lane] = psi;
     if (ST == ST_F32_LOCAL) L.rb2[j & 3][lane] = ref_of(mm.rho);
@@ -801,7 +807,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     double Fx, Fy;
     force(L.psi1[(j - 1) & 3], L.psi1[j & 3], L.psi1[(j + 1) & 3], mm.rho, Fx, Fy);
     Post<C> P;
-    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    P.init(m, mm.rho, mm.E, mm.ir, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
     const float *rn_m = L.rb1[(j - 1) & 3];
     const float *rn_0 = L.rb1[j & 3];
     const float *rn_p = L.rb1[(j + 1) & 3];
@@ -853,7 +859,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     double Fx, Fy;
     force(L.psi2[(j - 1) & 3], L.psi2[j & 3], L.psi2[(j + 1) & 3], mm.rho, Fx, Fy);
     Post<C> P;
-    P.init(m, mm.rho, mm.E, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    P.init(m, mm.rho, mm.E, mm.ir, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
     const float *rn_m = L.rb2[(j - 1) & 3];
     const float *rn_0 = L.rb2[j & 3];
     const float *rn_p = L.rb2[(j + 1) & 3];
@@ -1240,17 +1246,22 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *cc, hipStream_t s) {
   const unsigned grid = tile_grid(t);
-  if (t.bx != 256 || m.wall_x != 0 || !(m.beta_one || !m.sc_on)) return hipErrorInvalidValue;
-  switch (st) {
-    case ST_F32_GLOBAL:
-      hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
-      break;
-    case ST_F32_LOCAL:
-      hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  if ((t.bx != 64 && t.bx != 128 && t.bx != 256) || m.wall_x != 0 || !(m.beta_one || !m.sc_on))
+    return hipErrorInvalidValue;
+  if (st == ST_F32_GLOBAL && t.bx == 64)
+    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_LOCAL && t.bx == 64)
+    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_GLOBAL && t.bx == 128)
+    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_GLOBAL)
+    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_LOCAL && t.bx == 128)
+    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_LOCAL)
+    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -131,3 +131,18 @@ def test_pair_eligibility():
         assert g.get_step_pairing()[0] == want, (prec, extra)
         g.set_step_pairing(False)
         assert not g.get_step_pairing()[0]
+
+
+@pytest.mark.parametrize("bx", ["64", "128", "256"])
+def test_pair_block_widths(bx, monkeypatch):
+    """Every block width of the two-step kernel (64, 128 or 256 lanes;
+    6 halo columns each) gives the one-step result bit for bit."""
+    monkeypatch.setenv("LBM_PAIR_BX", bx)
+    Tc = inputs.cs_tc()
+    p, rho, T = inputs.static_droplet(nx=300, ny=70, radius=15, seed=11)
+    p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc, gy=-2e-5)
+    a = _run(p, rho, T, 41, CORRECTED, "fp32local", pair=False)
+    for rows in (0, 5):
+        say("case pair bx", bx, "rows", rows)
+        b = _run(p, rho, T, 41, CORRECTED, "fp32local", pair=True, rows=rows)
+        assert np.array_equal(a.get_state(), b.get_state()), (bx, rows)
