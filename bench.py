@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--steady-cases", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
+    ap.add_argument("--no-pair", action="store_true",
+                    help="one step per launch (the two-step kernel off)")
+    ap.add_argument("--traffic-out", default=TRAFFIC_FILE,
+                    help="where --traffic-from writes its summary")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="only summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, "
                          "then WRITE_SIZE) into the step kernel's HBM traffic file")
@@ -139,7 +143,7 @@ def traffic_summary(args):
     out["bytes_per_launch"] = out["fetch_bytes"] + out["write_bytes"]
     out["bytes_per_node"] = round(out["bytes_per_launch"] / (args.nx * args.ny), 1)
     out["bytes_per_node_step"] = round(out["bytes_per_node"] / out["steps_per_launch"], 1)
-    with open(TRAFFIC_FILE, "w") as fp:
+    with open(args.traffic_out, "w") as fp:
         json.dump(out, fp, indent=1)
         fp.write("\n")
     print(json.dumps(out), flush=True)
@@ -298,6 +302,8 @@ def main():
 
     g = Lattice(p, args.precision)
     g.init_fields(rho, T)
+    if args.no_pair:
+        g.set_step_pairing(False)
     g.set_check_interval(100)
     if args.warmup > 0:
         g.step(args.warmup, treatment)
