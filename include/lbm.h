@@ -220,7 +220,8 @@ const char *lbm_strerror(int status);
  * hipGraphs.  Each lattice keeps a single-lattice handle (lbm_batch_lattice)
  * for initialisation, moments, totals, residuals and checkpoints.  The step
  * is the same as lbm_step's, node for node, so a lattice advanced in a batch
- * is bitwise equal to the same lattice advanced alone.
+ * is bitwise equal to the same lattice advanced alone (also where either
+ * pairs steps).
  * ---------------------------------------------------------------------- */
 typedef struct lbm_batch_ctx *lbm_batch_handle;
 
@@ -252,9 +253,19 @@ int lbm_batch_set_active(lbm_batch_handle b, const int *active);
 int lbm_batch_set_tiling(lbm_batch_handle b, int bx, int rows);
 int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows);
 
-/* k = 0: one eager launch per step.  k even >= 2: lbm_batch_step replays a
- * hipGraph holding k step launches (captured on first use, recaptured when
- * the tiling or the active set changes) for every whole k steps. */
+/* Two steps per launch for the batch (see lbm_set_step_pairing): used when
+ * every lattice of the batch admits it, for the plain and corrected
+ * treatments; then each launch advances every active lattice two steps
+ * (one step for the last of an odd count).  `rows` (> 0) sets the band
+ * height of the two-step tiles, 0 keeps it.  Default: on, 8 rows.
+ * lbm_batch_get_step_pairing reports whether lbm_batch_step pairs steps. */
+int lbm_batch_set_step_pairing(lbm_batch_handle b, int on, int rows);
+int lbm_batch_get_step_pairing(lbm_batch_handle b, int *active, int *rows);
+
+/* k = 0: eager launches.  k even >= 2: lbm_batch_step replays a hipGraph
+ * holding k launches (k steps, or 2k with two steps per launch; captured
+ * on first use, recaptured when the tiling, the pairing or the active set
+ * changes) for every whole group. */
 int lbm_batch_use_graph(lbm_batch_handle b, int k);
 
 /* Synchronize and check every lattice (first failing status). */

@@ -1,8 +1,9 @@
-"""Tile-shape autotuner for the step kernel.
+"""Tile-shape autotuner for the step kernels.
 
-Times a few candidate tile shapes (lanes per block, rows per band) on a
-scratch copy of the work (a lattice or a batch built by `make`, so the
-caller's state is not advanced) and keeps the fastest.  Results are cached
+Times a few candidate tile shapes (lanes per block, rows per band) of the
+one-step kernel, or band heights of the two-step kernel, on a scratch copy
+of the work (a lattice or a batch built by `make`, so the caller's state is
+not advanced) and keeps the fastest.  Results are cached
 in a JSON file keyed by the device name, the storage form and the lattice
 sizes, so a later run of the same shape of work skips the timing.
 """
@@ -11,6 +12,8 @@ import json
 import os
 
 CANDIDATES = ((64, 4), (64, 8), (128, 4), (128, 8), (128, 16), (256, 4), (256, 8), (256, 16))
+# band heights of the two-step kernel
+PAIR_ROWS = (8, 12, 16, 20, 24)
 # single lattices also take 512-lane blocks (batches do not)
 SINGLE_CANDIDATES = CANDIDATES + ((512, 4), (512, 8))
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
@@ -63,6 +66,8 @@ def tune(make, kind, precision, sizes, treatment=1, steps=20, candidates=CANDIDA
         return tuple(cache[key]["best"]), cache[key].get("ms", {})
     obj = make()
     times = {}
+    if hasattr(obj, "set_step_pairing"):
+        obj.set_step_pairing(False)  # time the one-step kernel itself
     for bx, rows in candidates:
         obj.set_tiling(bx, rows)
         times["%d,%d" % (bx, rows)] = _time(obj, steps, treatment)
@@ -73,3 +78,27 @@ def tune(make, kind, precision, sizes, treatment=1, steps=20, candidates=CANDIDA
     if use_cache:
         _store(cache)
     return (bx, rows), times
+
+
+def tune_pair_rows(make, kind, precision, sizes, treatment=1, steps=20, candidates=PAIR_ROWS,
+                   use_cache=True):
+    """Fastest band height of the two-step kernel for the work `make()`
+    builds (steps even, so every launch pairs).  Returns (rows, {rows:
+    ms/step}), or (0, {}) when the work does not pair steps."""
+    key = _key(kind + "-pair", precision, sizes)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return int(cache[key]["best"]), cache[key].get("ms", {})
+    obj = make()
+    if not obj.get_step_pairing()[0]:
+        return 0, {}
+    times = {}
+    for rows in candidates:
+        obj.set_step_pairing(True, rows)
+        times[str(rows)] = _time(obj, steps + (steps & 1), treatment)
+    del obj
+    best = int(min(times, key=times.get))
+    cache[key] = {"best": best, "ms": times}
+    if use_cache:
+        _store(cache)
+    return best, times

@@ -3,8 +3,11 @@
 // Every lattice owns a slice of the batch workspace laid out exactly as a
 // single-lattice workspace, with its own lbm_ctx; the batch adds device
 // tables (models, buffer offsets, parities, clamp counters, tiles) and one
-// kernel launch per step that walks the tiles of all active lattices.  Whole
-// groups of k steps can be replayed from a captured hipGraph.
+// kernel launch per step, or per two steps where every lattice admits the
+// two-step kernel, that walks the tiles of all active lattices.  Whole
+// groups of k launches can be replayed from a captured hipGraph.  Every
+// launch swaps each active lattice's two buffers, so `parity` counts
+// launches, not steps.
 #include <stdlib.h>
 #include <string.h>
 
@@ -33,6 +36,9 @@ struct lbm_batch_ctx {
   int max_tiles;
   int ntiles;
   int bx, rows, pf;
+  BatchTile *d_ptiles;  // tiles of the two-step kernel
+  int nptiles;
+  int pair_ok, pair_on, prows;
   std::vector<int> active;
   std::vector<int> phase;  // host copy: lattice buffer = parity ^ phase
   int parity;
@@ -40,14 +46,14 @@ struct lbm_batch_ctx {
   hipStream_t cap;  // private stream the graphs are captured on
   hipGraphExec_t exec[2];
   hipGraph_t graph[2];
-  int have_graph[2];
+  int have_graph[2];  // 0, else 1 + treatment + 2 * (two-step launches)
 };
 
 namespace {
 
 struct BatchLayout {
   std::vector<size_t> lat_off, lat_bytes;
-  size_t off_models, off_off0, off_off1, off_phase, off_clamp, off_tiles;
+  size_t off_models, off_off0, off_off1, off_phase, off_clamp, off_tiles, off_ptiles;
   int max_tiles;
   size_t total;
 };
@@ -92,6 +98,8 @@ int batch_layout(int count, const lbm_params *p, BatchLayout *B) {
   off += align_up((size_t)count * sizeof(void *), kAlign);
   B->off_tiles = off;
   off += align_up((size_t)B->max_tiles * sizeof(BatchTile), kAlign);
+  B->off_ptiles = off;  // strips of 122 columns: never more than the bound above
+  off += align_up((size_t)B->max_tiles * sizeof(BatchTile), kAlign);
   B->total = off;
   return LBM_OK;
 }
@@ -134,6 +142,33 @@ int upload_tiles(lbm_batch_ctx *b) {
   if (!t.empty() && hipMemcpyAsync(b->d_tiles, t.data(), t.size() * sizeof(BatchTile),
                                    hipMemcpyHostToDevice, b->stream) != hipSuccess)
     return LBM_EDEVICE;
+  // two-step tiles: 128 lanes, strips of 122 owned columns
+  std::vector<BatchTile> pt;
+  if (b->pair_ok) {
+    for (int i = 0; i < b->count; ++i) {
+      if (!b->active[i]) continue;
+      const lbm_params &p = b->lat[i]->p;
+      const int strips = (p.nx + 121) / 122;
+      const int rows = b->prows < p.ny ? b->prows : p.ny;
+      const int bands = (p.ny + rows - 1) / rows;
+      for (int band = 0; band < bands; ++band)
+        for (int s = 0; s < strips; ++s) {
+          BatchTile x;
+          memset(&x, 0, sizeof(x));
+          x.lattice = i;
+          x.strip = s;
+          x.band = band;
+          x.rows = rows;
+          x.dir = 1;
+          pt.push_back(x);
+        }
+    }
+  }
+  if ((int)pt.size() > b->max_tiles) return LBM_EINVAL;
+  b->nptiles = (int)pt.size();
+  if (!pt.empty() && hipMemcpyAsync(b->d_ptiles, pt.data(), pt.size() * sizeof(BatchTile),
+                                    hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return LBM_EDEVICE;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
   drop_graphs(b);
   return LBM_OK;
@@ -159,31 +194,38 @@ int sync_phases(lbm_batch_ctx *b) {
   return LBM_OK;
 }
 
-BatchTables tables(const lbm_batch_ctx *b) {
+BatchTables tables(const lbm_batch_ctx *b, bool pairs) {
   BatchTables t;
   t.models = b->d_models;
   t.off0 = b->d_off0;
   t.off1 = b->d_off1;
   t.phase = b->d_phase;
   t.clamp = b->d_clamp;
-  t.tiles = b->d_tiles;
-  t.ntiles = b->ntiles;
+  t.tiles = pairs ? b->d_ptiles : b->d_tiles;
+  t.ntiles = pairs ? b->nptiles : b->ntiles;
   t.xcd = 1;
   return t;
 }
 
-void advance(lbm_batch_ctx *b, int n) {
+// `launches` launches of `per` steps each
+void advance(lbm_batch_ctx *b, int launches, int per) {
   for (int i = 0; i < b->count; ++i)
     if (b->active[i]) {
-      if (n & 1) b->lat[i]->cur ^= 1;
-      b->lat[i]->steps += n;
+      if (launches & 1) b->lat[i]->cur ^= 1;
+      b->lat[i]->steps += (long long)launches * per;
     }
-  if (n & 1) b->parity ^= 1;
+  if (launches & 1) b->parity ^= 1;
 }
 
-// Record graph_k step launches on the private stream (nothing runs); the
-// graph is then replayed on the caller's stream.
-int capture(lbm_batch_ctx *b, int treatment) {
+hipError_t launch(const lbm_batch_ctx *b, const BatchTables &t, bool pairs, int parity,
+                  int treatment, hipStream_t s) {
+  if (pairs) return lbmdev::launch_batch_pair(t, 128, b->st, b->ws, parity, treatment, s);
+  return lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, parity, treatment, s);
+}
+
+// Record graph_k launches on the private stream (nothing runs); the graph
+// is then replayed on the caller's stream.
+int capture(lbm_batch_ctx *b, int treatment, bool pairs) {
   const int par = b->parity;
   if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
     b->cap = nullptr;
@@ -191,10 +233,10 @@ int capture(lbm_batch_ctx *b, int treatment) {
   }
   if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return LBM_EDEVICE;
-  const BatchTables t = tables(b);
+  const BatchTables t = tables(b, pairs);
   hipError_t e = hipSuccess;
   for (int k = 0; k < b->graph_k && e == hipSuccess; ++k)
-    e = lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, par ^ (k & 1), treatment, b->cap);
+    e = launch(b, t, pairs, par ^ (k & 1), treatment, b->cap);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
   if ((e != hipSuccess || e2 != hipSuccess) && g) (void)hipGraphDestroy(g);
@@ -206,7 +248,7 @@ int capture(lbm_batch_ctx *b, int treatment) {
   }
   b->graph[par] = g;
   b->exec[par] = x;
-  b->have_graph[par] = 1 + treatment;  // remembers the treatment it was captured with
+  b->have_graph[par] = 1 + treatment + 2 * (int)pairs;  // what it was captured with
   return LBM_OK;
 }
 
@@ -252,6 +294,7 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   b->d_phase = (int *)(b->ws + B.off_phase);
   b->d_clamp = (unsigned long long **)(b->ws + B.off_clamp);
   b->d_tiles = (BatchTile *)(b->ws + B.off_tiles);
+  b->d_ptiles = (BatchTile *)(b->ws + B.off_ptiles);
   std::vector<lbmdev::Model> models(count);
   std::vector<long long> o0(count), o1(count);
   std::vector<unsigned long long *> cl(count);
@@ -274,6 +317,10 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   b->bx = maxnx >= 192 ? 256 : (maxnx > 62 ? 128 : 64);
   b->rows = 8;
   b->pf = t0.pf;
+  b->pair_ok = 1;
+  for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
+  b->pair_on = env_ll("LBM_PAIR", 1) != 0;
+  b->prows = (int)env_ll("LBM_PAIR_ROWS", 8) > 0 ? (int)env_ll("LBM_PAIR_ROWS", 8) : 8;
   hipError_t e = hipMemcpyAsync(b->d_models, models.data(), count * sizeof(lbmdev::Model),
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
@@ -323,27 +370,31 @@ int lbm_batch_step(lbm_batch_handle b, int n, int treatment) {
   int rc = sync_phases(b);
   if (rc) return rc;
   if (b->ntiles == 0) return LBM_OK;
-  while (b->graph_k >= 2 && n >= b->graph_k) {
+  const bool pairs = b->pair_on && b->pair_ok && b->nptiles > 0;
+  const int per = pairs ? 2 : 1;
+  while (b->graph_k >= 2 && n >= b->graph_k * per) {
     const int par = b->parity;
-    if (b->have_graph[par] && b->have_graph[par] != 1 + treatment) {
+    const int key = 1 + treatment + 2 * (int)pairs;
+    if (b->have_graph[par] && b->have_graph[par] != key) {
       (void)hipGraphExecDestroy(b->exec[par]);
       (void)hipGraphDestroy(b->graph[par]);
       b->have_graph[par] = 0;
     }
     if (!b->have_graph[par]) {
-      rc = capture(b, treatment);
+      rc = capture(b, treatment, pairs);
       if (rc) return rc;
     }
     if (hipGraphLaunch(b->exec[par], b->stream) != hipSuccess) return LBM_EDEVICE;
-    advance(b, b->graph_k);
-    n -= b->graph_k;
+    advance(b, b->graph_k, per);
+    n -= b->graph_k * per;
   }
-  const BatchTables t = tables(b);
-  for (int k = 0; k < n; ++k) {
-    if (lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, b->parity, treatment, b->stream) !=
-        hipSuccess)
+  // the rest eagerly: two-step launches, then one step if n is odd
+  while (n > 0) {
+    const bool two = pairs && n >= 2;
+    if (launch(b, tables(b, two), two, b->parity, treatment, b->stream) != hipSuccess)
       return LBM_EDEVICE;
-    advance(b, 1);
+    advance(b, 1, two ? 2 : 1);
+    n -= two ? 2 : 1;
   }
   return LBM_OK;
 }
@@ -361,6 +412,24 @@ int lbm_batch_set_tiling(lbm_batch_handle b, int bx, int rows) {
   b->bx = bx;
   b->rows = rows;
   return upload_tiles(b);
+}
+
+int lbm_batch_set_step_pairing(lbm_batch_handle b, int on, int rows) {
+  if (!b || rows < 0) return LBM_EINVAL;
+  b->pair_on = on != 0;
+  drop_graphs(b);
+  if (rows > 0 && rows != b->prows) {
+    b->prows = rows;
+    return upload_tiles(b);
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_get_step_pairing(lbm_batch_handle b, int *active, int *rows) {
+  if (!b || !active || !rows) return LBM_EINVAL;
+  *active = b->pair_on && b->pair_ok;
+  *rows = b->prows;
+  return LBM_OK;
 }
 
 int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows) {

@@ -126,5 +126,9 @@ struct BatchTables {
 };
 hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char *base, int parity,
                              int treatment, hipStream_t s);
+// Two steps of every lattice whose tiles the table lists (pair tiles:
+// strips of bx - 6 owned columns; bx 128; FP32 storage).
+hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, char *base, int parity,
+                             int treatment, hipStream_t s);
 
 }  // namespace lbmdev

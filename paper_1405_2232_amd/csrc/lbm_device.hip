@@ -644,19 +644,14 @@ struct PairLds {
   float rb2[4][BX];     // and after the second
 };
 
+// two steps on strip `strip` (owned columns strip * (BX - 6) ...) and
+// rows y0 .. y0 + n - 1 of one lattice
 template <int ST, int BX>
-__global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__restrict__ src_v,
-                                             void *__restrict__ dst_v, int treatment,
-                                             unsigned long long *clamp_counter) {
+__device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
+                          int strip, int y0, int n, int treatment,
+                          unsigned long long *clamp_counter, PairLds<BX> &L) {
   using S = float;
   using C = typename Prec<ST>::C;
-  __shared__ PairLds<BX> L;
-  const int tid = tile_of_block(t);
-  if (tid >= t.strips * t.bands) return;
-  const int strip = tid % t.strips;
-  const int band = tid / t.strips;
-  const int y0 = band * t.rows;
-  const int n = min(y0 + t.rows, m.ny) - y0;
   const Bufs sb = make_bufs<S>(src_v, m);
   const Bufs db = make_bufs<S>(dst_v, m);
   const unsigned pb = (unsigned)(m.plane * (long long)sizeof(S));
@@ -946,6 +941,40 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
     }
   }
   if (clamps && clamp_counter) atomicAdd(clamp_counter, (unsigned long long)clamps);
+}
+
+template <int ST, int BX>
+__global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__restrict__ src,
+                                             void *__restrict__ dst, int treatment,
+                                             unsigned long long *clamp_counter) {
+  __shared__ PairLds<BX> L;
+  const int tid = tile_of_block(t);
+  if (tid >= t.strips * t.bands) return;
+  const int strip = tid % t.strips;
+  const int y0 = (tid / t.strips) * t.rows;
+  pair_tile<ST, BX>(m, src, dst, strip, y0, min(y0 + t.rows, m.ny) - y0, treatment, clamp_counter, L);
+}
+
+// Two steps of many lattices: one block per tile of the pair tile list
+// (strips of BX - 6 owned columns).
+template <int ST, int BX>
+__global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restrict__ base,
+                                                   int parity, int treatment) {
+  __shared__ PairLds<BX> L;
+  int tid = blockIdx.x;
+  if (bt.xcd) {
+    const int per = (int)gridDim.x >> 3;
+    tid = (tid & 7) * per + (tid >> 3);
+  }
+  if (tid >= bt.ntiles) return;
+  const BatchTile t = bt.tiles[tid];
+  const Model m = bt.models[t.lattice];
+  const int sb = parity ^ bt.phase[t.lattice];
+  char *src = base + (sb ? bt.off1[t.lattice] : bt.off0[t.lattice]);
+  char *dst = base + (sb ? bt.off0[t.lattice] : bt.off1[t.lattice]);
+  const int y0 = t.band * t.rows;
+  pair_tile<ST, BX>(m, src, dst, t.strip, y0, min(y0 + t.rows, m.ny) - y0, treatment,
+                    bt.clamp[t.lattice], L);
 }
 
 // ---------------------------------------------------------------------------
@@ -1336,6 +1365,22 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) 
   if (blocks > 256 * 32) blocks = 256 * 32;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4 *)dst, (const u32x4 *)src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, char *base, int parity,
+                             int treatment, hipStream_t s) {
+  unsigned grid = (unsigned)t.ntiles;
+  if (t.xcd) grid = (grid + 7u) & ~7u;
+  if (grid == 0) return hipSuccess;
+  const dim3 g(grid);
+  if (bx != 128) return hipErrorInvalidValue;
+  if (st == ST_F32_GLOBAL)
+    hipLaunchKernelGGL((k_pair_batch<ST_F32_GLOBAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
+  else if (st == ST_F32_LOCAL)
+    hipLaunchKernelGGL((k_pair_batch<ST_F32_LOCAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -102,6 +102,8 @@ def lib():
             "lbm_batch_set_tiling": [vp, i, i],
             "lbm_batch_get_tiling": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
             "lbm_batch_use_graph": [vp, i],
+            "lbm_batch_set_step_pairing": [vp, i, i],
+            "lbm_batch_get_step_pairing": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
             "lbm_batch_sync": [vp],
             "lbm_batch_destroy": [vp],
         }
@@ -380,6 +382,17 @@ class Batch:
 
     def use_graph(self, k):
         _chk("lbm_batch_use_graph", lib().lbm_batch_use_graph(self._h, int(k)))
+
+    def set_step_pairing(self, on, rows=0):
+        _chk("lbm_batch_set_step_pairing",
+             lib().lbm_batch_set_step_pairing(self._h, int(bool(on)), int(rows)))
+
+    def get_step_pairing(self):
+        """(pairing used by step(), band height of the two-step tiles)"""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _chk("lbm_batch_get_step_pairing",
+             lib().lbm_batch_get_step_pairing(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), b.value
 
     def sync(self):
         return lib().lbm_batch_sync(self._h)

@@ -62,14 +62,17 @@ def _batch(cases, precision):
 def test_batch_equals_single_lattice_bitwise(precision):
     cases = _small_batch()
     ref = _single_states(cases, precision, 57, CORRECTED)
-    for tiling in (None, (64, 4), (128, 8), (256, 16)):
-        say("case batch", precision, tiling)
+    for tiling, pair in ((None, True), (None, False), ((64, 4), False), ((128, 8), True),
+                         ((256, 16), False)):
+        say("case batch", precision, tiling, "pairs", pair)
         b = _batch(cases, precision)
         if tiling:
             b.set_tiling(*tiling)
+        b.set_step_pairing(pair, 5 if tiling else 0)
+        assert b.get_step_pairing()[0] == (pair and precision != "fp64")
         b.step(57, CORRECTED)
         for i, m in enumerate(b.members):
-            assert np.array_equal(m.get_state(), ref[i]), (tiling, i)
+            assert np.array_equal(m.get_state(), ref[i]), (tiling, pair, i)
         b.close()
 
 
@@ -93,11 +96,12 @@ def test_batch_graph_replays_match_eager(precision):
     assert graph[0].totals()[6] == done
 
 
-def test_batch_active_mask_and_member_steps():
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+def test_batch_active_mask_and_member_steps(precision):
     """Frozen lattices keep their state; a member stepped on its own keeps
-    its own step parity inside the batch."""
+    its own step parity inside the batch (with two-step launches too)."""
     cases = _small_batch(5, seed=11)
-    b = _batch(cases, "fp64")
+    b = _batch(cases, precision)
     b.step(10, CORRECTED)
     b.set_active([1, 0, 1, 0, 1])
     b.step(7, CORRECTED)
@@ -106,7 +110,7 @@ def test_batch_active_mask_and_member_steps():
     b.step(6, CORRECTED)
     expect = [23, 16, 23, 19, 23]
     for i, (p, rho, T) in enumerate(cases):
-        ref = _single_states([(p, rho, T)], "fp64", expect[i], CORRECTED)[0]
+        ref = _single_states([(p, rho, T)], precision, expect[i], CORRECTED)[0]
         assert np.array_equal(b[i].get_state(), ref), i
         assert b[i].totals()[6] == expect[i]
 
