@@ -951,8 +951,12 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
   const int tid = tile_of_block(t);
   if (tid >= t.strips * t.bands) return;
   const int strip = tid % t.strips;
-  const int y0 = (tid / t.strips) * t.rows;
-  pair_tile<ST, BX>(m, src, dst, strip, y0, min(y0 + t.rows, m.ny) - y0, treatment, clamp_counter, L);
+  // t.bands bands over ny rows, heights differing by at most one row and
+  // the taller ones spread evenly (consecutive tiles share an XCD)
+  const int band = tid / t.strips;
+  const int y0 = (int)((long long)band * m.ny / t.bands);
+  const int y1 = (int)((long long)(band + 1) * m.ny / t.bands);
+  pair_tile<ST, BX>(m, src, dst, strip, y0, y1 - y0, treatment, clamp_counter, L);
 }
 
 // Two steps of many lattices: one block per tile of the pair tile list
