@@ -914,10 +914,16 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   };
 
   // the pipeline; register buffers alternate with the parity of j
-  Row<S> R[2], F[2];
+  // P holds the row after next: loaded an iteration before it is copied
+  // into its R slot, so a load has a whole iteration to arrive (the copy
+  // is 19 moves; loading into R directly would leave half an iteration)
+  Row<S> R[2], F[2], P;
   Mom<C> M[2], M2[2];
   const int J = n + 7;
-  if (wave_live) load_row(0, R[0]);
+  if (wave_live) {
+    load_row(0, R[0]);
+    load_row(1, P);
+  }
   for (int j0 = 0; j0 < J; j0 += 2) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -932,7 +938,8 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
         if (wave_live) {
           const int j1 = j - 1;
           if (j1 >= 1 && j1 < n + 5 && inside(vrow(j1))) collide_first(j1, R[u ^ 1], M[u ^ 1]);
-          if (j + 1 < n + 6) load_row(j + 1, R[u ^ 1]);
+          if (j + 1 < n + 6) R[u ^ 1] = P;
+          if (j + 2 < n + 6) load_row(j + 2, P);
           const int j4 = j - 4;
           if (j4 >= 3 && j4 < n + 3) collide_second(j4, F[u], M2[u]);
         }
