@@ -123,3 +123,58 @@ def test_strerror_names_every_status():
         assert msg and msg != "unknown status"
         seen.add(msg)
     assert len(seen) == 7
+
+
+def _host_handle(cfg, precision):
+    """A handle whose workspace pointer is never dereferenced on the host:
+    lbm_create only records offsets, so the pairing choice can be checked
+    without a GPU (nothing here launches or copies)."""
+    p = lbm.make_params(cfg, precision, 0.1, 0.08)
+    L = lbm.lib()
+    n = ctypes.c_size_t()
+    assert L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 40)  # 256-byte aligned, never touched
+    assert L.lbm_create(ctypes.byref(p), fake, n.value, None, ctypes.byref(h)) == 0
+    return L, h
+
+
+@pytest.mark.parametrize("nx,ny,rows", [(2048, 2048, 12), (4096, 4096, 14), (64, 64, 6), (300, 70, 6)])
+def test_two_step_band_height_without_gpu(nx, ny, rows, monkeypatch):
+    """The two-step band height the launch-round model picks (128-lane
+    blocks, four per CU, 256 CUs when no device answers): the fewest bands
+    minimising rounds x (2 r + 4)."""
+    monkeypatch.delenv("LBM_PAIR_ROWS", raising=False)
+    monkeypatch.delenv("LBM_PAIR_BX", raising=False)
+    cfg = dict(inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)[0], nx=nx, ny=ny)
+    L, h = _host_handle(cfg, "fp32local")
+    try:
+        a, r = ctypes.c_int(), ctypes.c_int()
+        assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
+        assert a.value == 1 and r.value == rows
+        # an explicit height: bands of at most that many rows
+        assert L.lbm_set_step_pairing(h, 1, 5) == 0
+        assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
+        assert r.value <= 5
+        assert L.lbm_set_step_pairing(h, 1, -1) == -1
+        assert L.lbm_set_step_pairing(h, 0, 0) == 0
+        assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
+        assert a.value == 0
+    finally:
+        L.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("precision,extra,want", [
+    ("fp32local", {}, 1), ("fp32dev", {}, 1), ("fp64", {}, 0),
+    ("fp32local", {"wall_x": True}, 0), ("fp32local", {"wall_x": "open", "u_in": 0.01}, 0),
+    ("fp32local", {"beta": 0.5}, 0), ("fp32local", {"G": 0.0, "beta": 0.5}, 1),
+    ("fp32local", {"wall_y": True}, 1)])
+def test_two_step_eligibility_without_gpu(precision, extra, want):
+    cfg = dict(inputs.static_droplet(nx=40, ny=30, radius=8, seed=1)[0], **extra)
+    L, h = _host_handle(cfg, precision)
+    try:
+        a, r = ctypes.c_int(), ctypes.c_int()
+        assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
+        assert a.value == want
+    finally:
+        L.lbm_destroy(h)
