@@ -146,3 +146,16 @@ def test_pair_block_widths(bx, monkeypatch):
         say("case pair bx", bx, "rows", rows)
         b = _run(p, rho, T, 41, CORRECTED, "fp32local", pair=True, rows=rows)
         assert np.array_equal(a.get_state(), b.get_state()), (bx, rows)
+
+
+def test_pair_full_size_wall_slab_bitwise():
+    """The benchmark's lattice and launch shape (2048 x 2048 wall slab,
+    default two-step tiling, periodic checks every 100 steps): 201 steps
+    paired give the one-step launches' state bit for bit."""
+    p, rho, T = inputs.wall_slab()
+    a = _run(p, rho, T, 201, CORRECTED, "fp32local", pair=False, check=100)
+    b = _run(p, rho, T, 201, CORRECTED, "fp32local", pair=True, check=100)
+    say("full-size pairing", b.get_step_pairing())
+    for x, y in zip(a.moments(), b.moments()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.get_state(), b.get_state())
