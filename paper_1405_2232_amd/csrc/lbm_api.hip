@@ -15,16 +15,43 @@ using lbmdev::Tiling;
 namespace lbmhost {
 
 
-// Default tile shape: wide strips (inner width bx - 2) and bands of 6 rows.
-// Short bands give many blocks (the step is latency-bound at two waves per
-// SIMD) and their two halo rows are re-read from L2 by the neighbouring band
-// running on the same XCD at the same time (2048^2: 6 rows 1.6 % faster than
-// 8 in FP64, 0.7 % in FP32; 12 and 16 rows slower).
+// Compute units of the current device (256 on MI355X).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 256;
+  return cus;
+}
+
+int one_step_bx(int nx) { return nx >= 192 ? 256 : (nx > 62 ? 128 : 64); }
+
+// Band height of the one-step kernel for `lanes` strip-rows (strips x rows,
+// summed over a batch's lattices) of blocks of bx lanes: `cap` rows when the
+// work fills the chip many times over, fewer (down to 2) when the blocks
+// would not fill the 2-waves-per-SIMD slots, because a block walks its band
+// row after row and small lattices are bound by that latency (eight 64^2
+// lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
+int one_step_rows(long long lanes, int bx, int cap) {
+  const long long slots = (long long)device_cus() * (512 / bx);
+  long long r = (lanes + slots - 1) / slots;
+  if (r < 2) r = 2;
+  if (r > cap) r = cap;
+  return (int)r;
+}
+
+// Default tile shape: wide strips (inner width bx - 2) and bands of 6 rows
+// (fewer on small lattices, see one_step_rows).  Short bands give many
+// blocks (the step is latency-bound at two waves per SIMD) and their two
+// halo rows are re-read from L2 by the neighbouring band running on the same
+// XCD at the same time (2048^2: 6 rows 1.6 % faster than 8 in FP64, 0.7 % in
+// FP32; 12 and 16 rows slower).
 Tiling default_tiling(int nx, int ny, int precision) {
   Tiling t;
-  t.bx = nx >= 192 ? 256 : (nx > 62 ? 128 : 64);
+  t.bx = one_step_bx(nx);
   t.strips = (nx + t.bx - 3) / (t.bx - 2);
-  t.rows = ny < 6 ? ny : 6;
+  t.rows = one_step_rows((long long)t.strips * ny, t.bx, 6);
+  if (t.rows > ny) t.rows = ny;
   t.bands = (ny + t.rows - 1) / t.rows;
   t.xcd = 1;
   t.alt = 1;
@@ -42,15 +69,6 @@ Tiling default_tiling(int nx, int ny, int precision) {
   t.nt = (int)env_ll("LBM_NT", t.nt);
   t.pf = (int)env_ll("LBM_PF", t.pf);
   return t;
-}
-
-// Compute units of the current device (256 on MI355X).
-static int device_cus() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    return 256;
-  return cus;
 }
 
 // Two-step tiling.  Blocks of 128 lanes (122 owned columns) run four to a
@@ -87,6 +105,22 @@ Tiling pair_tiling(int nx, int ny, int rows) {
   t.rows = (ny + t.bands - 1) / t.bands;  // the tallest band
   t.xcd = (int)env_ll("LBM_XCD", 1);
   t.alt = 0;
+  t.nt = 0;
+  t.pf = 1;
+  return t;
+}
+
+// Tiling of the moments and reduction launches: fixed (8-row bands), so
+// that the per-block partials buffer it sizes does not depend on the
+// device or the environment.
+Tiling moments_tiling(int nx, int ny) {
+  Tiling t;
+  t.bx = one_step_bx(nx);
+  t.strips = (nx + t.bx - 3) / (t.bx - 2);
+  t.rows = ny < 8 ? ny : 8;
+  t.bands = (ny + t.rows - 1) / t.rows;
+  t.xcd = 1;
+  t.alt = 1;
   t.nt = 0;
   t.pf = 1;
   return t;
@@ -150,7 +184,7 @@ bool compute_layout(const lbm_params *p, Layout *L) {
   off += align_up(4 * n * sizeof(double), kAlign);
   L->off_snap = off;
   off += align_up(2 * n * sizeof(double), kAlign);
-  Tiling t = default_tiling(p->nx, p->ny, p->precision);
+  Tiling t = moments_tiling(p->nx, p->ny);
   L->max_blocks = t.strips * t.bands;
   L->off_partials = off;
   off += align_up((size_t)L->max_blocks * lbmdev::kPartials * sizeof(double), kAlign);
@@ -337,7 +371,7 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->m = make_model(p, L);
   h->st = storage_of(p);
   h->t = default_tiling(p->nx, p->ny, p->precision);
-  h->tm = h->t;
+  h->tm = moments_tiling(p->nx, p->ny);
   h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0));
   h->pair_ok = h->st != lbmdev::ST_F64 && p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
   h->pair_on = env_ll("LBM_PAIR", 1) != 0;

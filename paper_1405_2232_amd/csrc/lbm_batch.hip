@@ -314,8 +314,10 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   Tiling t0 = b->lat[0]->t;
   int maxnx = 0;
   for (int i = 0; i < count; ++i) maxnx = p[i].nx > maxnx ? p[i].nx : maxnx;
-  b->bx = maxnx >= 192 ? 256 : (maxnx > 62 ? 128 : 64);
-  b->rows = 8;
+  b->bx = one_step_bx(maxnx);
+  long long lanes = 0;
+  for (int i = 0; i < count; ++i) lanes += (long long)((p[i].nx + b->bx - 3) / (b->bx - 2)) * p[i].ny;
+  b->rows = one_step_rows(lanes, b->bx, 8);
   b->pf = t0.pf;
   b->pair_ok = 1;
   for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
