@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"fp32local": 144, "fp32dev": 144, "fp64": 288}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic_wall_slab_2048.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1405_2232_amd", "csrc", f)
-                  for f in ("lbm_device.hip", "lbm_device.h")]
+                  for f in ("lbm_device.hip", "lbm_device.h", "lbm_api.hip")]
+# (lbm_api.hip holds the default tilings: a changed tiling changes the traffic)
 
 
 def kernel_hash():

@@ -257,7 +257,8 @@ int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows);
  * every lattice of the batch admits it, for the plain and corrected
  * treatments; then each launch advances every active lattice two steps
  * (one step for the last of an odd count).  `rows` (> 0) sets the band
- * height of the two-step tiles, 0 keeps it.  Default: on, 8 rows.
+ * height of the two-step tiles, 0 keeps it.  Default: on, with the band
+ * height chosen from the lattice sizes and the device's compute units.
  * lbm_batch_get_step_pairing reports whether lbm_batch_step pairs steps. */
 int lbm_batch_set_step_pairing(lbm_batch_handle b, int on, int rows);
 int lbm_batch_get_step_pairing(lbm_batch_handle b, int *active, int *rows);

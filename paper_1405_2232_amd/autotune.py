@@ -13,7 +13,7 @@ import os
 
 CANDIDATES = ((64, 4), (64, 8), (128, 4), (128, 8), (128, 16), (256, 4), (256, 8), (256, 16))
 # band heights of the two-step kernel
-PAIR_ROWS = (8, 12, 16, 20, 24)
+PAIR_ROWS = (12, 16, 24, 32, 48)
 # single lattices also take 512-lane blocks (batches do not)
 SINGLE_CANDIDATES = CANDIDATES + ((512, 4), (512, 8))
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")

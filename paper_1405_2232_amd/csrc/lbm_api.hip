@@ -32,6 +32,26 @@ int one_step_bx(int nx) { return nx >= 192 ? 256 : (nx > 62 ? 128 : 64); }
 // would not fill the 2-waves-per-SIMD slots, because a block walks its band
 // row after row and small lattices are bound by that latency (eight 64^2
 // lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
+int pair_rows_for(const long long *strips, const int *ny, int count) {
+  // the same round model as pair_tiling, for one band height shared by
+  // many lattices (128-lane blocks, four per CU)
+  const long long slots = (long long)device_cus() * 4;
+  int maxny = 1;
+  for (int i = 0; i < count; ++i) maxny = ny[i] > maxny ? ny[i] : maxny;
+  long long best = -1;
+  int rows = 6;
+  for (int r = 6; r <= (maxny > 6 ? maxny : 6); ++r) {
+    long long blocks = 0;
+    for (int i = 0; i < count; ++i) blocks += strips[i] * ((ny[i] + r - 1) / r);
+    const long long cost = ((blocks + slots - 1) / slots) * (2LL * r + 4);
+    if (best < 0 || cost < best) {
+      best = cost;
+      rows = r;
+    }
+  }
+  return rows;
+}
+
 int one_step_rows(long long lanes, int bx, int cap) {
   const long long slots = (long long)device_cus() * (512 / bx);
   long long r = (lanes + slots - 1) / slots;
@@ -77,10 +97,12 @@ Tiling default_tiling(int nx, int ny, int precision) {
 // A band of r rows costs its block about 2 r + 4 row collisions (the first
 // step also runs on two rows beyond each band edge), and the blocks of a
 // launch run in ceil(blocks / slots) rounds; rows <= 0 picks the fewest
-// bands (tallest band 6 to 16 rows) that minimise rounds x (2 r_max + 4).
-// At 2048^2 that is 171 bands of 12 rows (2907 blocks for 3 x 1024 slots);
-// more bands of the same tallest height filling the last round measured
-// no faster.  rows > 0 gives bands of at most `rows` rows.
+// bands (tallest band at least 6 rows) that minimise rounds x (2 r_max + 4).
+// That favours one round of tall bands: at 2048^2, 59 bands of 35 rows
+// (1003 blocks for 1024 slots, 0.101 ms per step against 0.118 with 12-row
+// bands in three rounds); at 4096^2, 30 bands of 137 rows (0.358 ms per
+// step against 0.420 at 14 rows).  rows > 0 gives bands of at most `rows`
+// rows.
 Tiling pair_tiling(int nx, int ny, int rows) {
   Tiling t;
   const long long ebx = env_ll("LBM_PAIR_BX", 128);
@@ -92,7 +114,7 @@ Tiling pair_tiling(int nx, int ny, int rows) {
     const long long slots = (long long)device_cus() * (512 / t.bx);
     long long best = -1;
     t.bands = 1;
-    for (int bands = (ny + 15) / 16; bands <= (ny + 5) / 6; ++bands) {
+    for (int bands = 1; bands <= (ny + 5) / 6; ++bands) {
       const long long blocks = (long long)t.strips * bands;
       const long long cost = ((blocks + slots - 1) / slots) * (2LL * ((ny + bands - 1) / bands) + 4);
       if (best < 0 || cost < best) {

@@ -322,7 +322,16 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   b->pair_ok = 1;
   for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
   b->pair_on = env_ll("LBM_PAIR", 1) != 0;
-  b->prows = (int)env_ll("LBM_PAIR_ROWS", 8) > 0 ? (int)env_ll("LBM_PAIR_ROWS", 8) : 8;
+  {
+    std::vector<long long> st(count);
+    std::vector<int> nys(count);
+    for (int i = 0; i < count; ++i) {
+      st[i] = (p[i].nx + 121) / 122;
+      nys[i] = p[i].ny;
+    }
+    const long long er = env_ll("LBM_PAIR_ROWS", 0);
+    b->prows = er > 0 ? (int)er : pair_rows_for(st.data(), nys.data(), count);
+  }
   hipError_t e = hipMemcpyAsync(b->d_models, models.data(), count * sizeof(lbmdev::Model),
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)

@@ -40,6 +40,7 @@ Tiling default_tiling(int nx, int ny, int precision);
 Tiling moments_tiling(int nx, int ny);
 int one_step_bx(int nx);
 int one_step_rows(long long lanes, int bx, int cap);
+int pair_rows_for(const long long *strips, const int *ny, int count);
 Tiling pair_tiling(int nx, int ny, int rows);
 int storage_of(const lbm_params *p);
 bool compute_layout(const lbm_params *p, Layout *L);

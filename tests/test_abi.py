@@ -139,7 +139,8 @@ def _host_handle(cfg, precision):
     return L, h
 
 
-@pytest.mark.parametrize("nx,ny,rows", [(2048, 2048, 12), (4096, 4096, 14), (64, 64, 6), (300, 70, 6)])
+@pytest.mark.parametrize("nx,ny,rows", [(2048, 2048, 35), (4096, 4096, 137), (1024, 1024, 10),
+                                        (64, 64, 6), (300, 70, 6)])
 def test_two_step_band_height_without_gpu(nx, ny, rows, monkeypatch):
     """The two-step band height the launch-round model picks (128-lane
     blocks, four per CU, 256 CUs when no device answers): the fewest bands
