@@ -195,14 +195,16 @@ int lbm_load(lbm_handle h, const char *path);
 int lbm_set_tiling(lbm_handle h, int bx, int rows);
 
 /* Two steps per kernel launch (temporal blocking).  Where the lattice
- * allows it (LBM_FP32_DEV or LBM_FP32_LOCAL storage, periodic in x, beta = 1
- * in Eq. (4) or G = 0) lbm_step advances the plain and corrected treatments
+ * allows it (any storage form, periodic in x, beta = 1 in Eq. (4) or
+ * G = 0) lbm_step advances the plain and corrected treatments
  * two steps per launch: the distributions of the intermediate time level
  * stay on chip, which halves the HBM traffic per step.  The arithmetic of
  * each step is the one-step kernel's.  `on` = 0 makes every step a
  * one-step launch; `rows` (> 0) sets the rows per block of the two-step
- * kernel, 0 keeps the current value.  Default: on, with the rows chosen
- * from the lattice size and the device's compute units.  A step that
+ * kernel, 0 keeps the current value.  Default: on for lattices large
+ * enough to fill the device (small ones are bound by latency, where
+ * one-step launches are faster), with the rows chosen from the lattice size
+ * and the device's compute units.  A step that
  * ends at a periodic check is always a one-step launch.
  * lbm_get_step_pairing reports whether lbm_step will pair steps (`active`)
  * and the rows per block.  LBM_EINVAL for a NULL handle or rows < 0. */
@@ -257,8 +259,9 @@ int lbm_batch_get_tiling(lbm_batch_handle b, int *bx, int *rows);
  * every lattice of the batch admits it, for the plain and corrected
  * treatments; then each launch advances every active lattice two steps
  * (one step for the last of an odd count).  `rows` (> 0) sets the band
- * height of the two-step tiles, 0 keeps it.  Default: on, with the band
- * height chosen from the lattice sizes and the device's compute units.
+ * height of the two-step tiles, 0 keeps it.  Default: on when the batch
+ * fills the device, with the band height chosen from the lattice sizes and
+ * the device's compute units.
  * lbm_batch_get_step_pairing reports whether lbm_batch_step pairs steps. */
 int lbm_batch_set_step_pairing(lbm_batch_handle b, int on, int rows);
 int lbm_batch_get_step_pairing(lbm_batch_handle b, int *active, int *rows);

@@ -32,10 +32,15 @@ int one_step_bx(int nx) { return nx >= 192 ? 256 : (nx > 62 ? 128 : 64); }
 // would not fill the 2-waves-per-SIMD slots, because a block walks its band
 // row after row and small lattices are bound by that latency (eight 64^2
 // lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
-int pair_rows_for(const long long *strips, const int *ny, int count) {
+// two-step blocks of bx lanes that fit on one CU: two waves per SIMD for
+// FP32 storage, one for FP64 (its LDS rings, 66 KB per 128 lanes, and its
+// registers allow no more)
+int pair_blocks_per_cu(int st, int bx) { return (st == lbmdev::ST_F64 ? 256 : 512) / bx; }
+
+int pair_rows_for(const long long *strips, const int *ny, int count, int st) {
   // the same round model as pair_tiling, for one band height shared by
-  // many lattices (128-lane blocks, four per CU)
-  const long long slots = (long long)device_cus() * 4;
+  // many lattices (128-lane blocks)
+  const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, 128);
   int maxny = 1;
   for (int i = 0; i < count; ++i) maxny = ny[i] > maxny ? ny[i] : maxny;
   long long best = -1;
@@ -50,6 +55,17 @@ int pair_rows_for(const long long *strips, const int *ny, int count) {
     }
   }
   return rows;
+}
+
+// Whether the work fills the chip: one-step blocks of bx lanes over
+// `lanes` strip-rows would need bands of at least 6 rows to occupy every
+// slot.  Smaller work is bound by the latency of each block's row walk,
+// where a two-step launch (about n + 7 dependent row iterations for two
+// steps of an n-row band) loses to two one-step launches with short bands
+// (eight 64^2 FP64 lattices: 15.4 us per step paired, 7.0 unpaired).
+bool fills_chip(long long lanes, int bx) {
+  const long long slots = (long long)device_cus() * (512 / bx);
+  return lanes >= 6 * slots;
 }
 
 int one_step_rows(long long lanes, int bx, int cap) {
@@ -103,15 +119,16 @@ Tiling default_tiling(int nx, int ny, int precision) {
 // bands in three rounds); at 4096^2, 30 bands of 137 rows (0.358 ms per
 // step against 0.420 at 14 rows).  rows > 0 gives bands of at most `rows`
 // rows.
-Tiling pair_tiling(int nx, int ny, int rows) {
+Tiling pair_tiling(int nx, int ny, int rows, int st) {
   Tiling t;
   const long long ebx = env_ll("LBM_PAIR_BX", 128);
   t.bx = ebx == 64 ? 64 : (ebx == 256 ? 256 : 128);
+  if (st == lbmdev::ST_F64) t.bx = 128;  // the only FP64 width built
   t.strips = (nx + t.bx - 7) / (t.bx - 6);
   if (rows > 0) {
     t.bands = (ny + rows - 1) / rows;
   } else {
-    const long long slots = (long long)device_cus() * (512 / t.bx);
+    const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, t.bx);
     long long best = -1;
     t.bands = 1;
     for (int bands = 1; bands <= (ny + 5) / 6; ++bands) {
@@ -394,9 +411,9 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->st = storage_of(p);
   h->t = default_tiling(p->nx, p->ny, p->precision);
   h->tm = moments_tiling(p->nx, p->ny);
-  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0));
-  h->pair_ok = h->st != lbmdev::ST_F64 && p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
-  h->pair_on = env_ll("LBM_PAIR", 1) != 0;
+  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0), h->st);
+  h->pair_ok = p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
+  h->pair_on = env_ll("LBM_PAIR", fills_chip((long long)h->t.strips * p->ny, h->t.bx) ? 1 : 0) != 0;
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char *)dev_workspace;
   h->buf[0] = h->ws + L.off_buf[0];
@@ -701,7 +718,7 @@ int lbm_set_tiling(lbm_handle h, int bx, int rows) {
 int lbm_set_step_pairing(lbm_handle h, int on, int rows) {
   if (!h || rows < 0) return LBM_EINVAL;
   h->pair_on = on != 0;
-  if (rows > 0) h->tp = lbmhost::pair_tiling(h->p.nx, h->p.ny, rows);
+  if (rows > 0) h->tp = lbmhost::pair_tiling(h->p.nx, h->p.ny, rows, h->st);
   return LBM_OK;
 }
 

@@ -321,7 +321,7 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   b->pf = t0.pf;
   b->pair_ok = 1;
   for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
-  b->pair_on = env_ll("LBM_PAIR", 1) != 0;
+  b->pair_on = env_ll("LBM_PAIR", fills_chip(lanes, b->bx) ? 1 : 0) != 0;
   {
     std::vector<long long> st(count);
     std::vector<int> nys(count);
@@ -330,7 +330,7 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
       nys[i] = p[i].ny;
     }
     const long long er = env_ll("LBM_PAIR_ROWS", 0);
-    b->prows = er > 0 ? (int)er : pair_rows_for(st.data(), nys.data(), count);
+    b->prows = er > 0 ? (int)er : pair_rows_for(st.data(), nys.data(), count, b->lat[0]->st);
   }
   hipError_t e = hipMemcpyAsync(b->d_models, models.data(), count * sizeof(lbmdev::Model),
                                 hipMemcpyHostToDevice, b->stream);

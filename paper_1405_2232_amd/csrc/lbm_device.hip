@@ -635,9 +635,9 @@ __global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__
 // same stored (FP32) values, so two one-step launches and one two-step
 // launch give the same result up to the compiler's contraction choices.
 
-template <int BX>
+template <int BX, typename S>
 struct PairLds {
-  float f1[3][18][BX];  // distributions after the first step, stored form
+  S f1[3][18][BX];      // distributions after the first step, stored form
   double psi1[4][BX];
   double psi2[4][BX];
   float rb1[4][BX];     // per-node references after the first step (ST_F32_LOCAL)
@@ -649,8 +649,8 @@ struct PairLds {
 template <int ST, int BX>
 __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
                           int strip, int y0, int n, int treatment,
-                          unsigned long long *clamp_counter, PairLds<BX> &L) {
-  using S = float;
+                          unsigned long long *clamp_counter, PairLds<BX, typename Prec<ST>::S> &L) {
+  using S = typename Prec<ST>::S;
   using C = typename Prec<ST>::C;
   const Bufs sb = make_bufs<S>(src_v, m);
   const Bufs db = make_bufs<S>(dst_v, m);
@@ -696,7 +696,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   };
 
   auto load_f1 = [&](int j, Row<S> &d) {
-    const float *f = &L.f1[j % 3][0][0];
+    const S *f = &L.f1[j % 3][0][0];
 #pragma unroll
     for (int q = 0; q < 18; ++q) d.v[q] = f[q * BX + lane];
     if (ST == ST_F32_LOCAL) d.rb = L.rb1[j & 3][lane];
@@ -727,7 +727,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
             v6 = (C)d.v[6], v7 = (C)d.v[7], v8 = (C)d.v[8];
     mm.jx = ((v1 - v3) + (v5 - v6)) + (v8 - v7);
     mm.jy = ((v2 - v4) + (v5 + v6)) - (v7 + v8);
-    const double ref = ST == ST_F32_GLOBAL ? m.rho_ref : (double)d.rb;
+    const double ref = ST == ST_F64 ? 0.0 : (ST == ST_F32_GLOBAL ? m.rho_ref : (double)d.rb);
     mm.sf = (C)a;
     mm.sg = (C)b;
     mm.rho = ref + a;
@@ -766,8 +766,10 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   // reference after it (rb_new)
   auto g_wall = [&](int i, C gs, double rho, float rb_old, float rb_new) {
     const double wE = Q9::ey[i] < 0 ? m.wall_E[2] : m.wall_E[3];
-    const double refE = ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_old * m.cvT_ref;
-    const double refEn = ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_new * m.cvT_ref;
+    const double refE = ST == ST_F64 ? 0.0
+                        : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_old * m.cvT_ref);
+    const double refEn = ST == ST_F64 ? 0.0
+                         : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref : (double)rb_new * m.cvT_ref);
     return -gs + wgt<C>(i) * (C)(2.0 * rho * wE - refE - refEn);
   };
 
@@ -807,16 +809,16 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     const float *rn_0 = L.rb1[j & 3];
     const float *rn_p = L.rb1[(j + 1) & 3];
     const bool wd = m.wall_y && v == 0, wu = m.wall_y && v == ny - 1;
-    float *fm = &L.f1[(j + 2) % 3][0][0];
-    float *f0 = &L.f1[j % 3][0][0];
-    float *fp = &L.f1[(j + 1) % 3][0][0];
+    S *fm = &L.f1[(j + 2) % 3][0][0];
+    S *f0 = &L.f1[j % 3][0][0];
+    S *fp = &L.f1[(j + 1) % 3][0][0];
     // every lane stores: the lanes that do not collide in this step (the
     // two edges of the block) write inside the ring row, into entries that
     // no owned column reads
     const int tl = lane > 0 ? lane - 1 : 0, tr = lane < BX - 1 ? lane + 1 : BX - 1;
     auto push = [&](int i, C fo, C go) {
       const int exi = Q9::ex[i], eyi = Q9::ey[i];
-      float *f = eyi > 0 ? fp : (eyi < 0 ? fm : f0);
+      S *f = eyi > 0 ? fp : (eyi < 0 ? fm : f0);
       const int to = exi > 0 ? tr : (exi < 0 ? tl : lane);
       f[i * BX + to] = (S)fo;
       f[(9 + i) * BX + to] = (S)go;
@@ -954,7 +956,7 @@ template <int ST, int BX>
 __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__restrict__ src,
                                              void *__restrict__ dst, int treatment,
                                              unsigned long long *clamp_counter) {
-  __shared__ PairLds<BX> L;
+  __shared__ PairLds<BX, typename Prec<ST>::S> L;
   const int tid = tile_of_block(t);
   if (tid >= t.strips * t.bands) return;
   const int strip = tid % t.strips;
@@ -971,7 +973,7 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
 template <int ST, int BX>
 __global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restrict__ base,
                                                    int parity, int treatment) {
-  __shared__ PairLds<BX> L;
+  __shared__ PairLds<BX, typename Prec<ST>::S> L;
   int tid = blockIdx.x;
   if (bt.xcd) {
     const int per = (int)gridDim.x >> 3;
@@ -1286,9 +1288,12 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *cc, hipStream_t s) {
   const unsigned grid = tile_grid(t);
-  if ((t.bx != 64 && t.bx != 128 && t.bx != 256) || m.wall_x != 0 || !(m.beta_one || !m.sc_on))
+  if ((t.bx != 64 && t.bx != 128 && t.bx != 256) || m.wall_x != 0 || !(m.beta_one || !m.sc_on) ||
+      (st == ST_F64 && t.bx != 128))
     return hipErrorInvalidValue;
-  if (st == ST_F32_GLOBAL && t.bx == 64)
+  if (st == ST_F64 && t.bx == 128)
+    hipLaunchKernelGGL((k_pair<ST_F64, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
+  else if (st == ST_F32_GLOBAL && t.bx == 64)
     hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
   else if (st == ST_F32_LOCAL && t.bx == 64)
     hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
@@ -1386,7 +1391,9 @@ hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, char *base, i
   if (grid == 0) return hipSuccess;
   const dim3 g(grid);
   if (bx != 128) return hipErrorInvalidValue;
-  if (st == ST_F32_GLOBAL)
+  if (st == ST_F64)
+    hipLaunchKernelGGL((k_pair_batch<ST_F64, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
+  else if (st == ST_F32_GLOBAL)
     hipLaunchKernelGGL((k_pair_batch<ST_F32_GLOBAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
   else if (st == ST_F32_LOCAL)
     hipLaunchKernelGGL((k_pair_batch<ST_F32_LOCAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);

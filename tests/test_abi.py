@@ -139,20 +139,23 @@ def _host_handle(cfg, precision):
     return L, h
 
 
-@pytest.mark.parametrize("nx,ny,rows", [(2048, 2048, 35), (4096, 4096, 137), (1024, 1024, 10),
-                                        (64, 64, 6), (300, 70, 6)])
-def test_two_step_band_height_without_gpu(nx, ny, rows, monkeypatch):
+@pytest.mark.parametrize("nx,ny,precision,rows", [
+    (2048, 2048, "fp32local", 35), (4096, 4096, "fp32local", 137), (1024, 1024, "fp32local", 10),
+    (64, 64, "fp32local", 6), (300, 70, "fp32local", 6), (2048, 2048, "fp64", 69)])
+def test_two_step_band_height_without_gpu(nx, ny, precision, rows, monkeypatch):
     """The two-step band height the launch-round model picks (128-lane
-    blocks, four per CU, 256 CUs when no device answers): the fewest bands
-    minimising rounds x (2 r + 4)."""
+    blocks, four per CU for FP32 storage and two for FP64, 256 CUs when no
+    device answers): the fewest bands minimising rounds x (2 r + 4)."""
     monkeypatch.delenv("LBM_PAIR_ROWS", raising=False)
     monkeypatch.delenv("LBM_PAIR_BX", raising=False)
     cfg = dict(inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)[0], nx=nx, ny=ny)
-    L, h = _host_handle(cfg, "fp32local")
+    L, h = _host_handle(cfg, precision)
     try:
         a, r = ctypes.c_int(), ctypes.c_int()
         assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
-        assert a.value == 1 and r.value == rows
+        # on by default only where the lattice fills the device
+        assert a.value == (1 if nx * ny >= 1024 * 1024 else 0) and r.value == rows
+        assert L.lbm_set_step_pairing(h, 1, 0) == 0
         # an explicit height: bands of at most that many rows
         assert L.lbm_set_step_pairing(h, 1, 5) == 0
         assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
@@ -166,7 +169,7 @@ def test_two_step_band_height_without_gpu(nx, ny, rows, monkeypatch):
 
 
 @pytest.mark.parametrize("precision,extra,want", [
-    ("fp32local", {}, 1), ("fp32dev", {}, 1), ("fp64", {}, 0),
+    ("fp32local", {}, 1), ("fp32dev", {}, 1), ("fp64", {}, 1),
     ("fp32local", {"wall_x": True}, 0), ("fp32local", {"wall_x": "open", "u_in": 0.01}, 0),
     ("fp32local", {"beta": 0.5}, 0), ("fp32local", {"G": 0.0, "beta": 0.5}, 1),
     ("fp32local", {"wall_y": True}, 1)])
@@ -175,6 +178,7 @@ def test_two_step_eligibility_without_gpu(precision, extra, want):
     L, h = _host_handle(cfg, precision)
     try:
         a, r = ctypes.c_int(), ctypes.c_int()
+        assert L.lbm_set_step_pairing(h, 1, 0) == 0  # a small lattice: off by default
         assert L.lbm_get_step_pairing(h, ctypes.byref(a), ctypes.byref(r)) == 0
         assert a.value == want
     finally:

@@ -2,7 +2,7 @@
 against the FP64 oracle.
 
 The two-step kernel runs the one-step kernel's arithmetic on the same
-stored FP32 values, so pairing steps must leave the state bit for bit
+stored values (FP32 or FP64), so pairing steps must leave the state bit for bit
 unchanged, and the result must meet the FP32 parity bar against the
 oracle.  Cases span several strips and bands with ragged tails, y walls
 (Dirichlet and adiabatic), gravity, odd step counts (a one-step launch at
@@ -11,7 +11,7 @@ shorter than one tile."""
 import numpy as np
 import pytest
 
-from gpu_util import compare_fp32dev, need_gpu, oracle_run, say
+from gpu_util import compare_fp32dev, compare_fp64, need_gpu, oracle_run, say
 from oracle import CORRECTED, PLAIN
 from paper_1405_2232_amd import inputs
 
@@ -63,7 +63,7 @@ def _cases():
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp32local", "fp32dev"])
+@pytest.mark.parametrize("precision", ["fp32local", "fp32dev", "fp64"])
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
 def test_pairs_equal_single_steps(case, precision):
     name, p, rho, T, steps, tr = case
@@ -80,6 +80,9 @@ def test_pairs_equal_single_steps(case, precision):
     if precision == "fp32local":
         o = oracle_run(p, rho, T, steps, tr)
         compare_fp32dev(b.moments(), o.moments(), what=("pair", name))
+    if precision == "fp64":
+        o = oracle_run(p, rho, T, steps, tr)
+        compare_fp64(b.moments(), o.moments(), what=("pair", name))
 
 
 def test_pair_rows_invariance():
@@ -122,12 +125,14 @@ def test_pair_clamp_count():
 def test_pair_eligibility():
     from paper_1405_2232_amd.lbm import Lattice
     p, rho, T = inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)
-    for prec, extra, want in (("fp32local", {}, True), ("fp32dev", {}, True), ("fp64", {}, False),
+    for prec, extra, want in (("fp32local", {}, True), ("fp32dev", {}, True), ("fp64", {}, True),
                               ("fp32local", {"wall_x": True}, False),
                               ("fp32local", {"beta": 0.5}, False),
                               ("fp32local", {"G": 0.0, "beta": 0.5}, True)):
         g = Lattice(dict(p, **extra), prec)
         g.init_fields(rho, T)
+        assert not g.get_step_pairing()[0]  # too small to pair by default
+        g.set_step_pairing(True)
         assert g.get_step_pairing()[0] == want, (prec, extra)
         g.set_step_pairing(False)
         assert not g.get_step_pairing()[0]

@@ -1,9 +1,10 @@
 """Compile-time resource check of the step kernels (CPU only, hipcc cross
 compiles for gfx950): no step or batch kernel may use scratch memory (a
 spilled row buffer costs 2.5x in throughput) or drop below two waves per
-SIMD.  The open-channel variants (mode 2, small lattices) may spill a few
-bytes but no row buffer (at most 64 bytes per lane); so may the two-step
-kernel, whose frame reserves a few bytes for spilled scalars."""
+SIMD (one for the FP64 two-step kernels, whose LDS rings allow no more).
+The open-channel variants (mode 2, small lattices) may spill a few bytes
+but no row buffer (at most 64 bytes per lane); so may the two-step kernel,
+whose frame reserves a few bytes for spilled scalars."""
 import os
 import re
 import subprocess
@@ -38,7 +39,10 @@ def test_step_kernels_use_no_scratch():
                 if int(m.group(1)) > limit:
                     bad.append((cur, "scratch", int(m.group(1))))
             m = re.search(r"Occupancy \[waves/SIMD\]: (\d+)", line)
-            if m and int(m.group(1)) < 2:
+            # the FP64 two-step kernels run one wave per SIMD by design (their
+            # LDS rings allow two 128-lane blocks per CU)
+            need = 1 if re.search(r"k_pair(_batch)?ILi0E", cur) else 2
+            if m and int(m.group(1)) < need:
                 bad.append((cur, "occupancy", int(m.group(1))))
     assert seen > 50
     assert not bad, bad
