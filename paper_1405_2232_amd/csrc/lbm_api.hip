@@ -108,7 +108,8 @@ Tiling default_tiling(int nx, int ny, int precision) {
 }
 
 // Two-step tiling.  Blocks of 128 lanes (122 owned columns) run four to a
-// CU (two waves per SIMD; the LDS rings take 40 KB per block).  The ny rows
+// CU for FP32 storage (two waves per SIMD; the LDS rings take 40 KB per
+// block), two for FP64 (66 KB; one wave per SIMD).  The ny rows
 // are split evenly into `bands` bands (heights differ by at most one row).
 // A band of r rows costs its block about 2 r + 4 row collisions (the first
 // step also runs on two rows beyond each band edge), and the blocks of a

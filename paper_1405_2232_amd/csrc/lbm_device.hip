@@ -612,10 +612,10 @@ __global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__
 // ---------------------------------------------------------------------------
 // Two time steps per launch (temporal blocking along the band).
 //
-// On lattices periodic in x, with FP32 storage and the force of Eq. (2)
-// alone, one launch advances the state by two steps and the distributions
-// of the intermediate time level never reach HBM, which halves the HBM
-// traffic per step.  A block of BX lanes covers BX consecutive columns; the
+// On lattices periodic in x, with the force of Eq. (2) alone, one launch
+// advances the state by two steps and the distributions of the
+// intermediate time level never reach HBM, which halves the HBM traffic per
+// step.  A block of BX lanes covers BX consecutive columns; the
 // inner BX - 6 lanes own a strip, and three halo columns per side supply
 // psi of the first step, the first step's pushes into the owned columns'
 // neighbours and psi of the second step.  At iteration j the block
@@ -624,16 +624,18 @@ __global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__
 //     first-step distributions became complete with the pushes of row j - 2
 //     (ring psi2; the distributions are kept in registers),
 //   - collides row j - 1 (first step) and pushes the results into an LDS
-//     ring of three rows,
-//   - loads row j + 1,
+//     ring of three rows (in the storage precision),
+//   - moves row j + 1 into place and loads row j + 2 into a spare register
+//     row,
 //   - collides row j - 4 (second step) and pushes the results to HBM with
 //     the same stores as the one-step kernel.
 // Rows are counted from three rows below the band (j = 0) to three rows
 // above it; at y walls rows outside the lattice are not collided and the
 // second step's psi ghost rows mirror the wall rows, as in the one-step
-// kernel.  The arithmetic of each step is the one-step kernel's, on the
-// same stored (FP32) values, so two one-step launches and one two-step
-// launch give the same result up to the compiler's contraction choices.
+// kernel.  The arithmetic of each step is the one-step kernel's (the shared
+// collision is written in explicit FMAs), on the same stored values, so two
+// one-step launches and one two-step launch give the same result bit for
+// bit.
 
 template <int BX, typename S>
 struct PairLds {
