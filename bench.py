@@ -118,7 +118,7 @@ def traffic_summary(args):
     written), then the per-launch mean over the step kernel's dispatches is
     written with the hash of the kernel sources it was taken on."""
     import re
-    step = re.compile(r"lbmdev::k_tile<(\d+), (\d+), 0, (\d+)>|lbmdev::k_pair<(\d+), (\d+)>")
+    step = re.compile(r"lbmdev::k_tile<(\d+), (\d+), 0, (\d+)>|lbmdev::k_pair<(\d+), (\d+)(?:, \w+)?>")
     out = {"precision": args.precision, "nx": args.nx, "ny": args.ny,
            "layout": "row-interleaved", "kernel_hash": kernel_hash()}
     copy_kib = float(1 << 20)

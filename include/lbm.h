@@ -195,8 +195,7 @@ int lbm_load(lbm_handle h, const char *path);
 int lbm_set_tiling(lbm_handle h, int bx, int rows);
 
 /* Two steps per kernel launch (temporal blocking).  Where the lattice
- * allows it (any storage form, periodic in x, beta = 1 in Eq. (4) or
- * G = 0) lbm_step advances the plain and corrected treatments
+ * allows it (any storage form and force, periodic in x) lbm_step advances the plain and corrected treatments
  * two steps per launch: the distributions of the intermediate time level
  * stay on chip, which halves the HBM traffic per step.  The arithmetic of
  * each step is the one-step kernel's.  `on` = 0 makes every step a

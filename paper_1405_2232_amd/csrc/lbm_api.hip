@@ -32,15 +32,23 @@ int one_step_bx(int nx) { return nx >= 192 ? 256 : (nx > 62 ? 128 : 64); }
 // would not fill the 2-waves-per-SIMD slots, because a block walks its band
 // row after row and small lattices are bound by that latency (eight 64^2
 // lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
-// two-step blocks of bx lanes that fit on one CU: two waves per SIMD for
-// FP32 storage, one for FP64 (its LDS rings, 66 KB per 128 lanes, and its
-// registers allow no more)
-int pair_blocks_per_cu(int st, int bx) { return (st == lbmdev::ST_F64 ? 256 : 512) / bx; }
+// two-step blocks of bx lanes that fit on one CU: at most two waves per
+// SIMD for FP32 storage and one for FP64 (registers), and no more than the
+// 160 KB of LDS hold (the rings: 3 x 18 distributions, 2 x 4 psi rows, 2 x
+// 4 references, and with the mixed force 2 x 4 psi^2 rows, per lane)
+int pair_blocks_per_cu(int st, int bx, bool mix) {
+  const int waves = st == lbmdev::ST_F64 ? 4 : 8;
+  const long long lds = (long long)bx * (54 * (st == lbmdev::ST_F64 ? 8 : 4) + 64 + 32 + (mix ? 64 : 0));
+  long long by_lds = 163840 / lds;
+  long long by_waves = waves / (bx / 64);
+  long long b = by_lds < by_waves ? by_lds : by_waves;
+  return b < 1 ? 1 : (int)b;
+}
 
-int pair_rows_for(const long long *strips, const int *ny, int count, int st) {
+int pair_rows_for(const long long *strips, const int *ny, int count, int st, bool mix) {
   // the same round model as pair_tiling, for one band height shared by
   // many lattices (128-lane blocks)
-  const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, 128);
+  const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, 128, mix);
   int maxny = 1;
   for (int i = 0; i < count; ++i) maxny = ny[i] > maxny ? ny[i] : maxny;
   long long best = -1;
@@ -120,16 +128,16 @@ Tiling default_tiling(int nx, int ny, int precision) {
 // bands in three rounds); at 4096^2, 30 bands of 137 rows (0.358 ms per
 // step against 0.420 at 14 rows).  rows > 0 gives bands of at most `rows`
 // rows.
-Tiling pair_tiling(int nx, int ny, int rows, int st) {
+Tiling pair_tiling(int nx, int ny, int rows, int st, bool mix) {
   Tiling t;
   const long long ebx = env_ll("LBM_PAIR_BX", 128);
   t.bx = ebx == 64 ? 64 : (ebx == 256 ? 256 : 128);
-  if (st == lbmdev::ST_F64) t.bx = 128;  // the only FP64 width built
+  if (st == lbmdev::ST_F64 || mix) t.bx = 128;  // the only width built for these
   t.strips = (nx + t.bx - 7) / (t.bx - 6);
   if (rows > 0) {
     t.bands = (ny + rows - 1) / rows;
   } else {
-    const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, t.bx);
+    const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, t.bx, mix);
     long long best = -1;
     t.bands = 1;
     for (int bands = 1; bands <= (ny + 5) / 6; ++bands) {
@@ -412,8 +420,9 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->st = storage_of(p);
   h->t = default_tiling(p->nx, p->ny, p->precision);
   h->tm = moments_tiling(p->nx, p->ny);
-  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0), h->st);
-  h->pair_ok = p->wall_x == 0 && (h->m.beta_one || !h->m.sc_on);
+  h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0), h->st,
+                      h->m.sc_on && !h->m.beta_one);
+  h->pair_ok = p->wall_x == 0;
   h->pair_on = env_ll("LBM_PAIR", fills_chip((long long)h->t.strips * p->ny, h->t.bx) ? 1 : 0) != 0;
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char *)dev_workspace;
@@ -719,7 +728,8 @@ int lbm_set_tiling(lbm_handle h, int bx, int rows) {
 int lbm_set_step_pairing(lbm_handle h, int on, int rows) {
   if (!h || rows < 0) return LBM_EINVAL;
   h->pair_on = on != 0;
-  if (rows > 0) h->tp = lbmhost::pair_tiling(h->p.nx, h->p.ny, rows, h->st);
+  if (rows > 0)
+    h->tp = lbmhost::pair_tiling(h->p.nx, h->p.ny, rows, h->st, h->m.sc_on && !h->m.beta_one);
   return LBM_OK;
 }
 

@@ -39,6 +39,7 @@ struct lbm_batch_ctx {
   BatchTile *d_ptiles;  // tiles of the two-step kernel
   int nptiles;
   int pair_ok, pair_on, prows;
+  bool pair_mix;  // some lattice uses the mixed force of Eq. (4)
   std::vector<int> active;
   std::vector<int> phase;  // host copy: lattice buffer = parity ^ phase
   int parity;
@@ -219,7 +220,7 @@ void advance(lbm_batch_ctx *b, int launches, int per) {
 
 hipError_t launch(const lbm_batch_ctx *b, const BatchTables &t, bool pairs, int parity,
                   int treatment, hipStream_t s) {
-  if (pairs) return lbmdev::launch_batch_pair(t, 128, b->st, b->ws, parity, treatment, s);
+  if (pairs) return lbmdev::launch_batch_pair(t, 128, b->st, b->pair_mix, b->ws, parity, treatment, s);
   return lbmdev::launch_batch_step(t, b->bx, b->pf, b->st, b->ws, parity, treatment, s);
 }
 
@@ -320,7 +321,11 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   b->rows = one_step_rows(lanes, b->bx, 8);
   b->pf = t0.pf;
   b->pair_ok = 1;
-  for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
+  b->pair_mix = false;
+  for (int i = 0; i < count; ++i) {
+    b->pair_ok = b->pair_ok && b->lat[i]->pair_ok;
+    b->pair_mix = b->pair_mix || (b->lat[i]->m.sc_on && !b->lat[i]->m.beta_one);
+  }
   b->pair_on = env_ll("LBM_PAIR", fills_chip(lanes, b->bx) ? 1 : 0) != 0;
   {
     std::vector<long long> st(count);
@@ -330,7 +335,7 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
       nys[i] = p[i].ny;
     }
     const long long er = env_ll("LBM_PAIR_ROWS", 0);
-    b->prows = er > 0 ? (int)er : pair_rows_for(st.data(), nys.data(), count, b->lat[0]->st);
+    b->prows = er > 0 ? (int)er : pair_rows_for(st.data(), nys.data(), count, b->lat[0]->st, b->pair_mix);
   }
   hipError_t e = hipMemcpyAsync(b->d_models, models.data(), count * sizeof(lbmdev::Model),
                                 hipMemcpyHostToDevice, b->stream);

@@ -80,9 +80,9 @@ inline int strip_width(int bx) { return bx - 2; }
 // Launchers (stream-ordered, no synchronization).  Return hipError_t.
 hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *clamp_counter, hipStream_t s);
-// Two steps in one launch (x periodic, beta = 1 or no interaction force;
-// bx 64, 128 or 256 for FP32 storage, 128 for FP64; strips of bx - 6 owned
-// columns): src holds time t, dst receives time t + 2.
+// Two steps in one launch (x periodic; bx 64, 128 or 256 for FP32 storage
+// with the force of Eq. (2), 128 for FP64 or the mixed force of Eq. (4);
+// strips of bx - 6 owned columns): src holds time t, dst receives t + 2.
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *clamp_counter, hipStream_t s);
 hipError_t launch_moments(const Model &m, const Tiling &t, int st, const void *src,
@@ -127,8 +127,9 @@ struct BatchTables {
 hipError_t launch_batch_step(const BatchTables &t, int bx, int pf, int st, char *base, int parity,
                              int treatment, hipStream_t s);
 // Two steps of every lattice whose tiles the table lists (pair tiles:
-// strips of bx - 6 owned columns; bx 128).
-hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, char *base, int parity,
+// strips of bx - 6 owned columns; bx 128; mix: some lattice uses the mixed
+// force of Eq. (4)).
+hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, bool mix, char *base, int parity,
                              int treatment, hipStream_t s);
 
 }  // namespace lbmdev

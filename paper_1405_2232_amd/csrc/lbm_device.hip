@@ -637,21 +637,24 @@ __global__ __launch_bounds__(BX) void k_batch(BatchTables bt, char *__restrict__
 // one-step launches and one two-step launch give the same result bit for
 // bit.
 
-template <int BX, typename S>
+template <int BX, typename S, bool MIX>
 struct PairLds {
   S f1[3][18][BX];      // distributions after the first step, stored form
   double psi1[4][BX];
   double psi2[4][BX];
   float rb1[4][BX];     // per-node references after the first step (ST_F32_LOCAL)
   float rb2[4][BX];     // and after the second
+  double s1[4][MIX ? BX : 1];  // psi^2 for the second term of Eq. (4)
+  double s2[4][MIX ? BX : 1];
 };
 
 // two steps on strip `strip` (owned columns strip * (BX - 6) ...) and
 // rows y0 .. y0 + n - 1 of one lattice
-template <int ST, int BX>
+// (MIX: the lattice uses the mixed force of Eq. (4), beta != 1)
+template <int ST, int BX, bool MIX>
 __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
                           int strip, int y0, int n, int treatment,
-                          unsigned long long *clamp_counter, PairLds<BX, typename Prec<ST>::S> &L) {
+                          unsigned long long *clamp_counter, PairLds<BX, typename Prec<ST>::S, MIX> &L) {
   using S = typename Prec<ST>::S;
   using C = typename Prec<ST>::C;
   const Bufs sb = make_bufs<S>(src_v, m);
@@ -737,9 +740,11 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     mm.ir = 1.0 / mm.rho;
   };
 
-  // Eq. (2) force (beta = 1) from a psi ring, plus the body force
-  auto force = [&](const double *pm, const double *p0, const double *pp, double rho, double &Fx,
-                   double &Fy) {
+  // force of Eq. (2), or of Eq. (4) with the psi^2 rings (MIX), from the
+  // rings' rows j - 1, j, j + 1, plus the body force
+  auto force = [&](const double (*ring)[BX], const double (*sring)[MIX ? BX : 1], int j,
+                   double rho, double &Fx, double &Fy) {
+    const double *pm = ring[(j - 1) & 3], *p0 = ring[j & 3], *pp = ring[(j + 1) & 3];
     Fx = 0.0;
     Fy = 0.0;
     if (m.sc_on) {
@@ -750,6 +755,16 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
       const double gb = -m.G * m.beta * p0[c];
       Fx = gb * sx;
       Fy = gb * sy;
+      if (MIX && !m.beta_one) {  // second term of Eq. (4), from psi^2
+        const double *qm = sring[(j - 1) & 3], *q0 = sring[j & 3], *qp = sring[(j + 1) & 3];
+        const double tx2 = (q0[c + 1] - q0[c - 1]) * (1.0 / 3.0) +
+                           ((qp[c + 1] - qp[c - 1]) + (qm[c + 1] - qm[c - 1])) * (1.0 / 12.0);
+        const double ty2 = (qp[c] - qm[c]) * (1.0 / 3.0) +
+                           ((qp[c + 1] + qp[c - 1]) - (qm[c + 1] + qm[c - 1])) * (1.0 / 12.0);
+        const double h = -m.G * 0.5 * (1.0 - m.beta);
+        Fx += h * tx2;
+        Fy += h * ty2;
+      }
     }
     Fx += rho * m.gx;
     Fy += rho * m.gy;
@@ -781,6 +796,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     int cl;
     node_psi(m, mm.rho, mm.E, mm.ir, psi, s, cl);
     L.psi1[j & 3][lane] = psi;
+    if (MIX) L.s1[j & 3][lane] = s;
     if (ST == ST_F32_LOCAL) L.rb1[j & 3][lane] = ref_of(mm.rho);
     const int v = vrow(j);
     if (own && v >= y0 && v < y0 + n) clamps += cl;
@@ -794,9 +810,16 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     node_psi(m, mm.rho, mm.E, mm.ir, psi, s, cl);
     const int v = vrow(j);
     L.psi2[j & 3][lane] = psi;
+    if (MIX) L.s2[j & 3][lane] = s;
     if (ST == ST_F32_LOCAL) L.rb2[j & 3][lane] = ref_of(mm.rho);
-    if (m.wall_y && v == 0) L.psi2[(j - 1) & 3][lane] = psi;  // mirror ghost rows
-    if (m.wall_y && v == ny - 1) L.psi2[(j + 1) & 3][lane] = psi;
+    if (m.wall_y && v == 0) {  // mirror ghost rows
+      L.psi2[(j - 1) & 3][lane] = psi;
+      if (MIX) L.s2[(j - 1) & 3][lane] = s;
+    }
+    if (m.wall_y && v == ny - 1) {
+      L.psi2[(j + 1) & 3][lane] = psi;
+      if (MIX) L.s2[(j + 1) & 3][lane] = s;
+    }
     if (own && v >= y0 && v < y0 + n) clamps += cl;
   };
 
@@ -804,7 +827,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   auto collide_first = [&](int j, const Row<S> &d, const Mom<C> &mm) {
     const int v = vrow(j);
     double Fx, Fy;
-    force(L.psi1[(j - 1) & 3], L.psi1[j & 3], L.psi1[(j + 1) & 3], mm.rho, Fx, Fy);
+    force(L.psi1, L.s1, j, mm.rho, Fx, Fy);
     Post<C> P;
     P.init(m, mm.rho, mm.E, mm.ir, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
     const float *rn_m = L.rb1[(j - 1) & 3];
@@ -856,7 +879,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   auto collide_second = [&](int j, const Row<S> &d, const Mom<C> &mm) {
     const int r = vrow(j);
     double Fx, Fy;
-    force(L.psi2[(j - 1) & 3], L.psi2[j & 3], L.psi2[(j + 1) & 3], mm.rho, Fx, Fy);
+    force(L.psi2, L.s2, j, mm.rho, Fx, Fy);
     Post<C> P;
     P.init(m, mm.rho, mm.E, mm.ir, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
     const float *rn_m = L.rb2[(j - 1) & 3];
@@ -954,11 +977,11 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   if (clamps && clamp_counter) atomicAdd(clamp_counter, (unsigned long long)clamps);
 }
 
-template <int ST, int BX>
+template <int ST, int BX, bool MIX>
 __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__restrict__ src,
                                              void *__restrict__ dst, int treatment,
                                              unsigned long long *clamp_counter) {
-  __shared__ PairLds<BX, typename Prec<ST>::S> L;
+  __shared__ PairLds<BX, typename Prec<ST>::S, MIX> L;
   const int tid = tile_of_block(t);
   if (tid >= t.strips * t.bands) return;
   const int strip = tid % t.strips;
@@ -967,15 +990,15 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
   const int band = tid / t.strips;
   const int y0 = (int)((long long)band * m.ny / t.bands);
   const int y1 = (int)((long long)(band + 1) * m.ny / t.bands);
-  pair_tile<ST, BX>(m, src, dst, strip, y0, y1 - y0, treatment, clamp_counter, L);
+  pair_tile<ST, BX, MIX>(m, src, dst, strip, y0, y1 - y0, treatment, clamp_counter, L);
 }
 
 // Two steps of many lattices: one block per tile of the pair tile list
 // (strips of BX - 6 owned columns).
-template <int ST, int BX>
+template <int ST, int BX, bool MIX>
 __global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restrict__ base,
                                                    int parity, int treatment) {
-  __shared__ PairLds<BX, typename Prec<ST>::S> L;
+  __shared__ PairLds<BX, typename Prec<ST>::S, MIX> L;
   int tid = blockIdx.x;
   if (bt.xcd) {
     const int per = (int)gridDim.x >> 3;
@@ -988,7 +1011,7 @@ __global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restr
   char *src = base + (sb ? bt.off1[t.lattice] : bt.off0[t.lattice]);
   char *dst = base + (sb ? bt.off0[t.lattice] : bt.off1[t.lattice]);
   const int y0 = t.band * t.rows;
-  pair_tile<ST, BX>(m, src, dst, t.strip, y0, min(y0 + t.rows, m.ny) - y0, treatment,
+  pair_tile<ST, BX, MIX>(m, src, dst, t.strip, y0, min(y0 + t.rows, m.ny) - y0, treatment,
                     bt.clamp[t.lattice], L);
 }
 
@@ -1290,25 +1313,31 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *cc, hipStream_t s) {
   const unsigned grid = tile_grid(t);
-  if ((t.bx != 64 && t.bx != 128 && t.bx != 256) || m.wall_x != 0 || !(m.beta_one || !m.sc_on) ||
-      (st == ST_F64 && t.bx != 128))
+  const bool mix = m.sc_on && !m.beta_one;
+  if ((t.bx != 64 && t.bx != 128 && t.bx != 256) || m.wall_x != 0 ||
+      ((st == ST_F64 || mix) && t.bx != 128))
     return hipErrorInvalidValue;
-  if (st == ST_F64 && t.bx == 128)
-    hipLaunchKernelGGL((k_pair<ST_F64, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_GLOBAL && t.bx == 64)
-    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_LOCAL && t.bx == 64)
-    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 64>), dim3(grid), dim3(64), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_GLOBAL && t.bx == 128)
-    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_GLOBAL)
-    hipLaunchKernelGGL((k_pair<ST_F32_GLOBAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_LOCAL && t.bx == 128)
-    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 128>), dim3(grid), dim3(128), 0, s, m, t, src, dst, treatment, cc);
-  else if (st == ST_F32_LOCAL)
-    hipLaunchKernelGGL((k_pair<ST_F32_LOCAL, 256>), dim3(grid), dim3(256), 0, s, m, t, src, dst, treatment, cc);
-  else
+#define LBM_P(ST_, B_, MIX_) \
+  hipLaunchKernelGGL((k_pair<ST_, B_, MIX_>), dim3(grid), dim3(B_), 0, s, m, t, src, dst, treatment, cc)
+  if (mix) {
+    if (st == ST_F64) LBM_P(ST_F64, 128, true);
+    else if (st == ST_F32_GLOBAL) LBM_P(ST_F32_GLOBAL, 128, true);
+    else if (st == ST_F32_LOCAL) LBM_P(ST_F32_LOCAL, 128, true);
+    else return hipErrorInvalidValue;
+  } else if (st == ST_F64) {
+    LBM_P(ST_F64, 128, false);
+  } else if (st == ST_F32_GLOBAL) {
+    if (t.bx == 64) LBM_P(ST_F32_GLOBAL, 64, false);
+    else if (t.bx == 128) LBM_P(ST_F32_GLOBAL, 128, false);
+    else LBM_P(ST_F32_GLOBAL, 256, false);
+  } else if (st == ST_F32_LOCAL) {
+    if (t.bx == 64) LBM_P(ST_F32_LOCAL, 64, false);
+    else if (t.bx == 128) LBM_P(ST_F32_LOCAL, 128, false);
+    else LBM_P(ST_F32_LOCAL, 256, false);
+  } else {
     return hipErrorInvalidValue;
+  }
+#undef LBM_P
   return hipGetLastError();
 }
 
@@ -1386,21 +1415,28 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, char *base, int parity,
+hipError_t launch_batch_pair(const BatchTables &t, int bx, int st, bool mix, char *base, int parity,
                              int treatment, hipStream_t s) {
   unsigned grid = (unsigned)t.ntiles;
   if (t.xcd) grid = (grid + 7u) & ~7u;
   if (grid == 0) return hipSuccess;
   const dim3 g(grid);
   if (bx != 128) return hipErrorInvalidValue;
-  if (st == ST_F64)
-    hipLaunchKernelGGL((k_pair_batch<ST_F64, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
-  else if (st == ST_F32_GLOBAL)
-    hipLaunchKernelGGL((k_pair_batch<ST_F32_GLOBAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
-  else if (st == ST_F32_LOCAL)
-    hipLaunchKernelGGL((k_pair_batch<ST_F32_LOCAL, 128>), g, dim3(128), 0, s, t, base, parity, treatment);
-  else
+#define LBM_PB(ST_, MIX_) \
+  hipLaunchKernelGGL((k_pair_batch<ST_, 128, MIX_>), g, dim3(128), 0, s, t, base, parity, treatment)
+  if (st == ST_F64) {
+    if (mix) LBM_PB(ST_F64, true);
+    else LBM_PB(ST_F64, false);
+  } else if (st == ST_F32_GLOBAL) {
+    if (mix) LBM_PB(ST_F32_GLOBAL, true);
+    else LBM_PB(ST_F32_GLOBAL, false);
+  } else if (st == ST_F32_LOCAL) {
+    if (mix) LBM_PB(ST_F32_LOCAL, true);
+    else LBM_PB(ST_F32_LOCAL, false);
+  } else {
     return hipErrorInvalidValue;
+  }
+#undef LBM_PB
   return hipGetLastError();
 }
 

@@ -171,7 +171,7 @@ def test_two_step_band_height_without_gpu(nx, ny, precision, rows, monkeypatch):
 @pytest.mark.parametrize("precision,extra,want", [
     ("fp32local", {}, 1), ("fp32dev", {}, 1), ("fp64", {}, 1),
     ("fp32local", {"wall_x": True}, 0), ("fp32local", {"wall_x": "open", "u_in": 0.01}, 0),
-    ("fp32local", {"beta": 0.5}, 0), ("fp32local", {"G": 0.0, "beta": 0.5}, 1),
+    ("fp32local", {"beta": 0.5}, 1), ("fp32local", {"G": 0.0, "beta": 0.5}, 1),
     ("fp32local", {"wall_y": True}, 1)])
 def test_two_step_eligibility_without_gpu(precision, extra, want):
     cfg = dict(inputs.static_droplet(nx=40, ny=30, radius=8, seed=1)[0], **extra)

@@ -150,3 +150,20 @@ def test_batch_256_uneven_lattices(precision):
             ta = float(np.abs(mg[3] - mo[3]).max())
             say("batch256 lattice", i, p["nx"], p["ny"], rr, ta)
             assert rr <= FP32_RHO_REL and ta <= FP32_T_ABS
+
+
+@pytest.mark.parametrize("precision", ["fp32local", "fp64"])
+def test_batch_mixed_force_pairs_bitwise(precision):
+    """A batch mixing the force of Eq. (2) with the mixed force of Eq. (4)
+    (beta != 1) in two-step launches: every lattice equals its one-step
+    single-lattice run bit for bit."""
+    cases = _small_batch(4, seed=13)
+    for k, beta in enumerate((1.0, 0.5, 1.0, 0.8)):
+        cases[k][0]["beta"] = beta
+    ref = _single_states(cases, precision, 31, CORRECTED)
+    b = _batch(cases, precision)
+    b.set_step_pairing(True, 7)
+    assert b.get_step_pairing()[0]
+    b.step(31, CORRECTED)
+    for i, m in enumerate(b.members):
+        assert np.array_equal(m.get_state(), ref[i]), i

@@ -60,6 +60,20 @@ def _cases():
     p, rho, T = inputs.static_droplet(nx=20, ny=5, radius=3, seed=17)
     p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc)
     out.append(("20x5 walls", p, rho, T, 99, CORRECTED))
+    # the mixed force of Eq. (4)
+    p, rho, T = inputs.static_droplet(nx=260, ny=45, radius=10, seed=13)
+    p.update(beta=0.5, gx=1e-5, wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc)
+    out.append(("260x45 beta=0.5 walls", p, rho, T, 151, CORRECTED))
+    # ideal EOS with beta = 0 (the model of the paper's Section III),
+    # periodic in x
+    n = 50
+    x = np.arange(n)[None, :]
+    rho = np.ones((40, n)) * (1.0 + 0.01 * np.sin(2 * np.pi * x / n))
+    T = np.ones((40, n)) * (1.0 + 0.03 * np.cos(2 * np.pi * x / n))
+    p = dict(nx=n, ny=40, tau_f=0.8, tau_g=0.5 + 0.3 / 0.71, G=1.0, beta=0.0, eos="ideal",
+             R=1.0 / 3.0, cv=1.0, wall_y=True, thermal_bottom="dirichlet", thermal_top="adiabatic",
+             T_bottom=1.03, gy=-1e-4)
+    out.append(("50x40 ideal beta=0", p, rho, T, 200, PLAIN))
     return out
 
 
@@ -127,7 +141,7 @@ def test_pair_eligibility():
     p, rho, T = inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)
     for prec, extra, want in (("fp32local", {}, True), ("fp32dev", {}, True), ("fp64", {}, True),
                               ("fp32local", {"wall_x": True}, False),
-                              ("fp32local", {"beta": 0.5}, False),
+                              ("fp32local", {"beta": 0.5}, True),
                               ("fp32local", {"G": 0.0, "beta": 0.5}, True)):
         g = Lattice(dict(p, **extra), prec)
         g.init_fields(rho, T)
