@@ -1,5 +1,10 @@
 // HIP kernels (gfx950) of the fused D2Q9 thermal pseudopotential LB step.
 //
+// Two kernels carry the step.  The one-step kernel (k_tile, k_batch) is
+// described here; the two-step kernel (k_pair, k_pair_batch), which runs the
+// same per-node arithmetic twice per launch with the intermediate time
+// level in LDS, is described where it is defined.
+//
 // One step is one launch.  A block of BX lanes covers BX consecutive
 // columns: the inner BX-2 lanes own a strip of columns, the two outer lanes
 // supply the psi halo.  The block walks a band of rows (a sliding window
@@ -137,7 +142,7 @@ struct Row {
 
 template <typename C>
 struct Mom {
-  double rho, E, ir;  // ir = 1/rho
+  double rho, E, ir;  // ir = 1/rho (carried by the two-step kernel only)
   C jx, jy;  // first moment of f
   C sf, sg;  // deviation sums (rho - ref, E - ref * cvT_ref)
 };
