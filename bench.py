@@ -5,16 +5,22 @@ Workload: the 2048 x 2048 flat two-phase slab (liquid in the middle half,
 Carnahan-Starling EOS at 0.85 T_c, walls at 0.80 T_c and 0.90 T_c, periodic
 in x), corrected temperature treatment (Eq. (24)), EOS at the local
 temperature, distributions stored in FP32 with a per-node density reference
-(the storage form that meets the FP64 oracle's tolerances).  One step = one
-fused launch (moments, psi, force, collision of f and g, streaming with
-bounce-back walls); the FP64 reduction check runs every 100 steps and the
-FP64 moments are exported once at the end of the timed region.
+(the storage form that meets the FP64 oracle's tolerances).  A step is the
+fused update (moments, psi, force, collision of f and g, streaming with
+bounce-back walls); the library runs two steps per launch (the two-step
+kernel) unless `--no-pair`; the FP64 reduction check runs every 100 steps
+(a one-step launch ends at each) and the FP64 moments are exported once at
+the end of the timed region.
 
 Prints one JSON line.  `value` is MLUPS (lattice updates per second / 1e6)
-with the state resident in HBM.  `roofline` prices the step kernel's
-algorithmic bytes (18 distributions read + written per node, 144 B in FP32)
-against the 8 TB/s HBM peak; `cpu_baseline` times the FP64 oracle on the
-host cores over a bounded number of steps of the same workload.
+with the state resident in HBM.  `roofline` prices the dominant kernel's
+algorithmic bytes (18 distributions read + written per node and step, 144
+B in FP32, times the steps per launch) against the 8 TB/s HBM peak, gives
+the launch time measured with HIP events, and the counter-measured HBM
+bytes per launch (`traffic`, from the profile summary while the kernel and
+tiling sources are unchanged) with the rate they imply (`measured_GBs`);
+`cpu_baseline` times the FP64 oracle on the host cores over a bounded
+number of steps of the same workload.
 """
 import argparse
 import hashlib
