@@ -9,8 +9,8 @@ temperature, distributions stored in FP32 with a per-node density reference
 fused update (moments, psi, force, collision of f and g, streaming with
 bounce-back walls); the library runs two steps per launch (the two-step
 kernel) unless `--no-pair`; the FP64 reduction check runs every 100 steps
-(a one-step launch ends at each) and the FP64 moments are exported once at
-the end of the timed region.
+(an even interval, so no pair straddles a check) and the FP64 moments are
+exported once at the end of the timed region.
 
 Prints one JSON line.  `value` is MLUPS (lattice updates per second / 1e6)
 with the state resident in HBM.  `roofline` prices the dominant kernel's
