@@ -20,7 +20,8 @@ the launch time measured with HIP events, and the counter-measured HBM
 bytes per launch (`traffic`, from the profile summary while the kernel and
 tiling sources are unchanged) with the rate they imply (`measured_GBs`);
 `cpu_baseline` times the FP64 oracle on the host cores over a bounded
-number of steps of the same workload.
+number of steps of the same workload, and again on one core
+(`single_core`, a child process with one OpenMP thread).
 """
 import argparse
 import hashlib
@@ -250,10 +251,40 @@ def cpu_baseline(p, rho, T, treatment, seconds):
             break
     cells = p["nx"] * p["ny"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d steps of the %dx%d slab (FP64 oracle, %d OpenMP threads, %.1f s)"
-                      % (n, p["nx"], p["ny"], cores, el)}
+    out = {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+           "kind": "oracle",
+           "sample": "%d steps of the %dx%d slab (FP64 oracle, %d OpenMP threads, %.1f s)"
+                     % (n, p["nx"], p["ny"], cores, el)}
+    out["single_core"] = single_core_baseline(p["nx"], p["ny"], treatment, seconds / 2)
+    return out
+
+
+def single_core_baseline(nx, ny, treatment, seconds):
+    """The same oracle steps on one host core, in a child process started
+    with OMP_NUM_THREADS=1 (the OpenMP runtime reads it at start-up); the
+    child imports no GPU code."""
+    import subprocess
+    code = ("import json, sys, time; sys.path.insert(0, %r)\n"
+            "from oracle import Oracle\n"
+            "from paper_1405_2232_amd import inputs\n"
+            "p, rho, T = inputs.wall_slab(nx=%d, ny=%d)\n"
+            "o = Oracle(p); o.init_fields(rho, T); o.step(1, %d)\n"
+            "n = 0; t0 = time.perf_counter()\n"
+            "while True:\n"
+            "    o.step(1, %d); n += 1; el = time.perf_counter() - t0\n"
+            "    if el >= %r: break\n"
+            "print(json.dumps({'steps': n, 's': el}))\n"
+            % (ROOT, nx, ny, treatment, treatment, float(seconds)))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=120 + 4 * seconds)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
+    return {"value": round(nx * ny * d["steps"] / d["s"] / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "sample": "%d steps of the %dx%d slab (FP64 oracle, 1 thread, %.1f s)"
+                      % (d["steps"], nx, ny, d["s"])}
 
 
 WARM_WEIGHTS = os.path.join(ROOT, "paper_1405_2232_amd", "warmstart_64.npz")
