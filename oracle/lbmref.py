@@ -154,6 +154,19 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("lbmref_init_fields: %d" % rc)
 
+    def init_fields_physical(self, rho, T, ux=None, uy=None):
+        """Equilibrium start whose velocity in the forcing scheme of Eq. (1)
+        (Sec. II: u = (j + F/2)/rho) is the given u: f = f_eq(rho, u -
+        F/(2 rho)) and g = cv T f.  F is the total force of the given rho
+        and T (psi of Eq. (2) or (4) depends on them alone, and so does the
+        body force), read from a first equilibrium start."""
+        r = _f64(rho, self.n).reshape(self.ny, self.nx)
+        self.init_fields(r, T)
+        Fx, Fy = self.force()
+        u = 0.0 if ux is None else _f64(ux, self.n).reshape(self.ny, self.nx)
+        v = 0.0 if uy is None else _f64(uy, self.n).reshape(self.ny, self.nx)
+        self.init_fields(r, T, u - 0.5 * Fx / r, v - 0.5 * Fy / r)
+
     def step(self, n, treatment):
         return lib().lbmref_step(self._h, int(n), int(treatment))
 
