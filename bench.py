@@ -295,7 +295,9 @@ def steady_section(count, torch, n=64, target=1e-8, cap=600000):
     cases (seeds 100000.., n x n, 1-3 droplets between Dirichlet walls, EOS
     at T0, FP64 storage): plain = one lattice at a time from the initial
     fields; batched = all cases in one batch; warm = batched, started from
-    the trained network's prediction (inference and screening timed in)."""
+    the trained network's prediction (inference and screening timed in);
+    physical_start = the batched runs again, each lattice started at rest
+    in the forcing scheme's velocity (stored momentum -F/2)."""
     from paper_1405_2232_amd import inputs, warmstart
     cases = [inputs.warmstart_case(100000 + s, n=n, max_drops=3) for s in range(count)]
     plain = warmstart.solve_single(cases, target=target, cap=cap)
@@ -319,6 +321,26 @@ def steady_section(count, torch, n=64, target=1e-8, cap=600000):
             "steps_cold_vs_warm_on_both": [sum(cold["steps"][i] for i in both), sum(warm["steps"][i] for i in both)],
             "speedup_warm_vs_plain": round(plain["wall_s"] / (warm["wall_s"] + t_inf), 2)})
     out["speedup_batched_vs_plain"] = round(plain["wall_s"] / cold["wall_s"], 2)
+    coldp = warmstart.solve(cases, target=target, cap=cap, keep=False, physical=True)
+    both = [i for i in range(count) if cold["steps"][i] is not None and coldp["steps"][i] is not None]
+    ps = {"cold_s": round(coldp["wall_s"], 2),
+          "cold_converged": sum(s is not None for s in coldp["steps"]),
+          "steps_cold_vs_physical_on_both": [sum(cold["steps"][i] for i in both),
+                                             sum(coldp["steps"][i] for i in both)],
+          "speedup_vs_plain": round(plain["wall_s"] / coldp["wall_s"], 2)}
+    if os.path.exists(WARM_WEIGHTS):
+        t0 = time.perf_counter()
+        preds = ws.predict(cases)
+        inits, _, _ = warmstart.screen(cases, preds)
+        t_inf = time.perf_counter() - t0
+        warmp = warmstart.solve(cases, inits=inits, target=target, cap=cap, keep=False, physical=True)
+        both = [i for i in range(count) if cold["steps"][i] is not None and warmp["steps"][i] is not None]
+        ps.update({"warm_s": round(warmp["wall_s"] + t_inf, 2),
+                   "warm_converged": sum(s is not None for s in warmp["steps"]),
+                   "steps_cold_vs_warm_on_both": [sum(cold["steps"][i] for i in both),
+                                                  sum(warmp["steps"][i] for i in both)],
+                   "speedup_warm_vs_plain": round(plain["wall_s"] / (warmp["wall_s"] + t_inf), 2)})
+    out["physical_start"] = ps
     return out
 
 

@@ -143,6 +143,19 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
 int lbm_init_fields(lbm_handle h, const double *rho, const double *ux, const double *uy,
                     const double *T);
 
+/* The same, with the stored momentum j = rho u - F/2 (f_i = f_i^eq(rho,
+ * u - F/(2 rho)), g_i = cv T f_i), F the total force (Eq. (2) or (4) plus
+ * the body force) of the given rho and T: with the forcing of Eq. (1)
+ * (Sec. II) the velocity is (j + F/2)/rho, so the velocity lbm_moments
+ * reports for this state is the given u (to rounding).  A state at rest
+ * with a density interface holds j = -F/2 at steady state; starting there
+ * shortens the solve to steady state.  Uses the second distribution
+ * buffer as scratch before the first step.  Same arguments and errors as
+ * lbm_init_fields, plus LBM_EDEVICE if a kernel launch fails (the handle
+ * is then uninitialised). */
+int lbm_init_fields_physical(lbm_handle h, const double *rho, const double *ux, const double *uy,
+                             const double *T);
+
 /* Enqueue n >= 1 time steps with the given treatment (it may change from
  * call to call).  Does not synchronize unless a check interval is set
  * (lbm_set_check_interval), in which case the status of the last check
@@ -243,6 +256,9 @@ int lbm_batch_init_fields(lbm_batch_handle b, int i, const double *rho, const do
                           const double *uy, const double *T);
 int lbm_batch_moments(lbm_batch_handle b, int i, double *rho, double *ux, double *uy,
                       double *T);
+/* lbm_init_fields_physical of lattice i. */
+int lbm_batch_init_fields_physical(lbm_batch_handle b, int i, const double *rho, const double *ux,
+                                   const double *uy, const double *T);
 
 /* Enqueue n >= 1 steps of every active lattice (all must be initialised). */
 int lbm_batch_step(lbm_batch_handle b, int n, int treatment);

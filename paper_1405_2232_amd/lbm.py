@@ -75,6 +75,7 @@ def lib():
             "lbm_workspace_bytes": [P, ctypes.POINTER(sz)],
             "lbm_create": [P, vp, sz, vp, ctypes.POINTER(vp)],
             "lbm_init_fields": [vp, dp, dp, dp, dp],
+            "lbm_init_fields_physical": [vp, dp, dp, dp, dp],
             "lbm_step": [vp, i, i],
             "lbm_set_check_interval": [vp, i],
             "lbm_sync": [vp],
@@ -96,6 +97,7 @@ def lib():
             "lbm_batch_create": [i, P, vp, sz, vp, ctypes.POINTER(vp)],
             "lbm_batch_lattice": [vp, i, ctypes.POINTER(vp)],
             "lbm_batch_init_fields": [vp, i, dp, dp, dp, dp],
+            "lbm_batch_init_fields_physical": [vp, i, dp, dp, dp, dp],
             "lbm_batch_moments": [vp, i, dp, dp, dp, dp],
             "lbm_batch_step": [vp, i, i],
             "lbm_batch_set_active": [vp, ctypes.POINTER(i)],
@@ -182,13 +184,14 @@ class _HandleOps:
     def handle(self):
         return self._h
 
-    def _init(self, rho, T, ux=None, uy=None):
+    def _init(self, rho, T, ux=None, uy=None, physical=False):
         n = self.n
         r, t = _host(rho, n), _host(T, n)
         u = _host(ux, n) if ux is not None else None
         v = _host(uy, n) if uy is not None else None
-        _chk("lbm_init_fields", lib().lbm_init_fields(self._h, _dp(r), _dp(u) if u is not None else None,
-                                                      _dp(v) if v is not None else None, _dp(t)))
+        name = "lbm_init_fields_physical" if physical else "lbm_init_fields"
+        _chk(name, getattr(lib(), name)(self._h, _dp(r), _dp(u) if u is not None else None,
+                                        _dp(v) if v is not None else None, _dp(t)))
 
     def step(self, n, treatment, check=True):
         rc = lib().lbm_step(self._h, int(n), int(treatment))
@@ -292,14 +295,17 @@ class Lattice(_HandleOps):
                                             n.value, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
         self._h = h
 
-    def init_fields(self, rho, T, ux=None, uy=None):
+    def init_fields(self, rho, T, ux=None, uy=None, physical=False):
+        """Equilibrium distributions of rho, u, T; `physical` stores the
+        momentum rho u - F/2 so that the reported velocity (j + F/2)/rho is
+        u (lbm_init_fields_physical)."""
         r, t = _host(rho, self.n), _host(T, self.n)
         rho_ref = self._rho_ref if self._rho_ref is not None else float(r.mean())
         T_ref = self._T_ref if self._T_ref is not None else float(t.mean())
         if self._h is None or (self.precision != "fp64" and
                                (rho_ref != self._p.rho_ref or T_ref != self._p.T_ref)):
             self._create(rho_ref, T_ref)
-        self._init(r, t, ux, uy)
+        self._init(r, t, ux, uy, physical)
 
     def close(self):
         if self._h is not None:
@@ -320,8 +326,8 @@ class _Member(_HandleOps):
         self._h = h
         self.nx, self.ny = nx, ny
 
-    def init_fields(self, rho, T, ux=None, uy=None):
-        self._init(rho, T, ux, uy)
+    def init_fields(self, rho, T, ux=None, uy=None, physical=False):
+        self._init(rho, T, ux, uy, physical)
 
 
 class Batch:

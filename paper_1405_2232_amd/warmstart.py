@@ -27,10 +27,12 @@ def _scalars(cases, Tc):
 
 
 def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=1000,
-          treatment=CORRECTED, graph=10, keep=True):
+          treatment=CORRECTED, graph=10, keep=True, physical=False):
     """Run every case (a list of (params, rho, T)) from its initial fields
     (or from inits[i] = (rho, T) when given) to the residual target, in one
-    batch with converged lattices frozen.  Checks the residual every
+    batch with converged lattices frozen.  `physical` starts each lattice
+    at rest in the forcing scheme's velocity (stored momentum -F/2,
+    lbm_init_fields_physical) instead of at zero stored momentum.  Checks the residual every
     `chunk` steps.  FP64 storage by default: with FP32 storage the one-step
     residual stalls between 1e-7 and 1e-6 (rounding of the stored
     distributions).  Returns a dict with per-case steps (None when the cap or
@@ -42,9 +44,9 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
     b = Batch([c[0] for c in cases], precision, refs=refs)
     for i, (m, (p, rho, T)) in enumerate(zip(b.members, cases)):
         if inits is not None and inits[i] is not None:
-            m.init_fields(*inits[i])
+            m.init_fields(*inits[i], physical=physical)
         else:
-            m.init_fields(rho, T)
+            m.init_fields(rho, T, physical=physical)
     if graph:
         b.use_graph(graph)
     n = len(cases)
