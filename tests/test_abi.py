@@ -3,6 +3,7 @@ include/lbm.h declares, and its parameter validation works without a GPU
 (no compute call is made here)."""
 import ctypes
 
+import numpy as np
 import pytest
 
 from paper_1405_2232_amd import inputs, lbm
@@ -106,6 +107,20 @@ def test_create_rejects_small_or_misaligned_workspace():
     assert L.lbm_step(h, 1, lbm.PLAIN) == lbm.ESTATE
     assert L.lbm_step(h, 0, lbm.PLAIN) == lbm.EINVAL
     assert L.lbm_step(h, 1, 7) == lbm.EINVAL
+    # both starts validate the host fields before any copy
+    n = p["nx"] * p["ny"]
+    good = np.full(n, 0.1)
+    bad = good.copy()
+    bad[n // 2] = 0.0
+    for fn in (L.lbm_init_fields, L.lbm_init_fields_physical):
+        assert fn(None, lbm._dp(good), None, None, lbm._dp(good)) == lbm.EINVAL
+        assert fn(h, None, None, None, lbm._dp(good)) == lbm.EINVAL
+        assert fn(h, lbm._dp(bad), None, None, lbm._dp(good)) == lbm.EINVAL
+        nan_u = good.copy()
+        nan_u[3] = np.nan
+        assert fn(h, lbm._dp(good), lbm._dp(nan_u), None, lbm._dp(good)) == lbm.EINVAL
+    assert L.lbm_batch_init_fields_physical(None, 0, lbm._dp(good), None, None,
+                                            lbm._dp(good)) == lbm.EINVAL
     assert L.lbm_set_tiling(h, 96, 4) == lbm.EINVAL
     assert L.lbm_set_tiling(h, 128, 0) == lbm.EINVAL
     assert L.lbm_set_tiling(h, 128, 5) == lbm.OK
