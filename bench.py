@@ -331,12 +331,13 @@ def steady_section(count, torch, n=64, target=1e-8, cap=600000):
     if os.path.exists(WARM_WEIGHTS):
         t0 = time.perf_counter()
         preds = ws.predict(cases)
-        inits, _, _ = warmstart.screen(cases, preds)
+        inits, _, _ = warmstart.screen(cases, preds, physical=True)
         t_inf = time.perf_counter() - t0
         warmp = warmstart.solve(cases, inits=inits, target=target, cap=cap, keep=False, physical=True)
         both = [i for i in range(count) if cold["steps"][i] is not None and warmp["steps"][i] is not None]
         ps.update({"warm_s": round(warmp["wall_s"] + t_inf, 2),
                    "warm_converged": sum(s is not None for s in warmp["steps"]),
+                   "warm_accepted": sum(p is not None for p in inits),
                    "steps_cold_vs_warm_on_both": [sum(cold["steps"][i] for i in both),
                                                   sum(warmp["steps"][i] for i in both)],
                    "speedup_warm_vs_plain": round(plain["wall_s"] / (warmp["wall_s"] + t_inf), 2)})

@@ -212,15 +212,15 @@ class WarmStart:
         return out
 
 
-def residuals(cases, fields, precision="fp64", treatment=CORRECTED):
+def residuals(cases, fields, precision="fp64", treatment=CORRECTED, physical=False):
     """One-step residual of each (rho, T) used as an initial state (inf
-    where the step fails)."""
+    where the step fails); `physical` as in solve."""
     refs = [(float(r.mean()), float(t.mean())) for _, r, t in cases]
     b = Batch([c[0] for c in cases], precision, refs=refs)
     out = []
     for m, fr in zip(b.members, fields):
         try:
-            m.init_fields(*fr)
+            m.init_fields(*fr, physical=physical)
             r = m.step_residual(treatment)
         except RuntimeError:
             r = np.inf
@@ -229,14 +229,16 @@ def residuals(cases, fields, precision="fp64", treatment=CORRECTED):
     return out
 
 
-def screen(cases, preds, precision="fp64", reject=1e-3, factor=3.0, treatment=CORRECTED):
+def screen(cases, preds, precision="fp64", reject=1e-3, factor=3.0, treatment=CORRECTED,
+           physical=False):
     """Keep a prediction as the initial state when its one-step residual is
     at most `reject` or at most `factor` times the cold start's own initial
     residual (a cold start of these two-phase states already has a one-step
     residual of about 3e-2, so an absolute 1e-3 alone would reject every
     start); otherwise, or when non-finite, None (the cold start).  Returns
-    (kept, predicted residuals, cold residuals)."""
-    rp = residuals(cases, preds, precision, treatment)
-    rc = residuals(cases, [(c[1], c[2]) for c in cases], precision, treatment)
+    (kept, predicted residuals, cold residuals).  `physical` judges both
+    from the start at rest in the forcing scheme (as in solve)."""
+    rp = residuals(cases, preds, precision, treatment, physical)
+    rc = residuals(cases, [(c[1], c[2]) for c in cases], precision, treatment, physical)
     keep = [pr if (r <= reject or r <= factor * c) else None for pr, r, c in zip(preds, rp, rc)]
     return keep, rp, rc
