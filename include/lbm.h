@@ -263,7 +263,9 @@ int lbm_batch_init_fields_physical(lbm_batch_handle b, int i, const double *rho,
 /* Enqueue n >= 1 steps of every active lattice (all must be initialised). */
 int lbm_batch_step(lbm_batch_handle b, int n, int treatment);
 
-/* Which lattices the next steps advance (active[i] != 0); NULL = all. */
+/* Which lattices the next steps advance (active[i] != 0); NULL = all.  A
+ * changed mask rebuilds the tile lists and drops the captured graphs; an
+ * unchanged one keeps both. */
 int lbm_batch_set_active(lbm_batch_handle b, const int *active);
 
 /* Tile shape shared by the batch (bx in 64/128/256 lanes, rows >= 1). */
