@@ -76,6 +76,42 @@ def test_batch_equals_single_lattice_bitwise(precision):
         b.close()
 
 
+def _tiny_batch():
+    """Six lattices of 40-100 columns whose rows all fit one round of
+    one-row 64-lane tiles; walls and gravity on two of them."""
+    rng = np.random.default_rng(21)
+    Tc = inputs.cs_tc()
+    out = []
+    for k in range(6):
+        nx, ny = int(rng.integers(40, 101)), int(rng.integers(20, 61))
+        p, rho, T = inputs.static_droplet(nx=nx, ny=ny, radius=0.25 * min(nx, ny),
+                                          T_ratio=float(rng.uniform(0.82, 0.9)), seed=300 + k)
+        if k % 3 == 2:
+            p.update(wall_y=True, T_bottom=0.8 * Tc, T_top=0.9 * Tc, gy=-1e-5)
+        out.append((p, rho, T))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local", "fp32dev"])
+def test_small_batch_one_row_tiles_bitwise(precision):
+    """A batch this small defaults to one-row 64-lane tiles; eager steps,
+    graph replays and an unchanged activity mask between them give the
+    single-lattice states bit for bit."""
+    cases = _tiny_batch()
+    ref = _single_states(cases, precision, 61, CORRECTED)
+    say("case tiny batch", precision)
+    b = _batch(cases, precision)
+    assert b.get_tiling() == (64, 1)
+    assert not b.get_step_pairing()[0]
+    b.use_graph(10)
+    for chunk in (7, 20, 1, 33):
+        b.set_active(None)  # unchanged: keeps the captured graphs
+        b.step(chunk, CORRECTED)
+    for i, m in enumerate(b.members):
+        assert np.array_equal(m.get_state(), ref[i]), i
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32local"])
 def test_batch_graph_replays_match_eager(precision):
     """Graph replays interleaved with eager steps and host syncs; every
