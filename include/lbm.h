@@ -263,6 +263,15 @@ int lbm_batch_init_fields_physical(lbm_batch_handle b, int i, const double *rho,
 /* Enqueue n >= 1 steps of every active lattice (all must be initialised). */
 int lbm_batch_step(lbm_batch_handle b, int n, int treatment);
 
+/* lbm_step_residual of every active lattice at once: one step of the
+ * batch between two moment passes, one wait.  residuals[i] and status[i]
+ * (count entries, caller-owned host arrays) get lattice i's residual and
+ * the status its lbm_step_residual would return (LBM_ENONFINITE,
+ * LBM_EDOMAIN or LBM_OK); an inactive lattice gets -1 and LBM_OK.  The
+ * return value is LBM_OK, or the error of a failed call (LBM_EINVAL,
+ * LBM_ESTATE for an uninitialised active lattice, LBM_EDEVICE). */
+int lbm_batch_step_residuals(lbm_batch_handle b, int treatment, double *residuals, int *status);
+
 /* Which lattices the next steps advance (active[i] != 0); NULL = all.  A
  * changed mask rebuilds the tile lists and drops the captured graphs; an
  * unchanged one keeps both. */

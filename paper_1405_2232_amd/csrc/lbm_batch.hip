@@ -435,6 +435,41 @@ int lbm_batch_step(lbm_batch_handle b, int n, int treatment) {
   return LBM_OK;
 }
 
+int lbm_batch_step_residuals(lbm_batch_handle b, int treatment, double *residuals, int *status) {
+  if (!b || !residuals || !status) return LBM_EINVAL;
+  if (treatment != LBM_PLAIN && treatment != LBM_CORRECTED) return LBM_EINVAL;
+  for (int i = 0; i < b->count; ++i)
+    if (b->active[i] && !b->lat[i]->initialized) return LBM_ESTATE;
+  // everything is enqueued on the batch's stream before the first wait
+  for (int i = 0; i < b->count; ++i) {
+    if (!b->active[i]) continue;
+    const int rc = run_moments(b->lat[i], nullptr, nullptr, nullptr, nullptr, 1, 0);
+    if (rc) return rc;
+  }
+  int rc = lbm_batch_step(b, 1, treatment);
+  if (rc) return rc;
+  for (int i = 0; i < b->count; ++i) {
+    if (!b->active[i]) continue;
+    rc = run_moments(b->lat[i], nullptr, nullptr, nullptr, nullptr, 0, 1);
+    if (rc) return rc;
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
+  for (int i = 0; i < b->count; ++i) {
+    residuals[i] = -1.0;
+    status[i] = LBM_OK;
+    if (!b->active[i]) continue;
+    double red[lbmdev::kPartials];
+    unsigned long long clamps = 0;
+    rc = fetch_totals(b->lat[i], red, &clamps);
+    if (rc) return rc;
+    const double r1 = red[6] > 0.0 ? red[5] / red[6] : 0.0;
+    const double r2 = red[8] > 0.0 ? red[7] / red[8] : 0.0;
+    residuals[i] = r1 > r2 ? r1 : r2;
+    status[i] = status_of(b->lat[i], red, clamps);
+  }
+  return LBM_OK;
+}
+
 int lbm_batch_set_active(lbm_batch_handle b, const int *active) {
   if (!b) return LBM_EINVAL;
   bool same = true;

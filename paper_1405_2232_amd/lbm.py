@@ -100,6 +100,7 @@ def lib():
             "lbm_batch_init_fields_physical": [vp, i, dp, dp, dp, dp],
             "lbm_batch_moments": [vp, i, dp, dp, dp, dp],
             "lbm_batch_step": [vp, i, i],
+            "lbm_batch_step_residuals": [vp, i, dp, ctypes.POINTER(i)],
             "lbm_batch_set_active": [vp, ctypes.POINTER(i)],
             "lbm_batch_set_tiling": [vp, i, i],
             "lbm_batch_get_tiling": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
@@ -370,6 +371,14 @@ class Batch:
 
     def step(self, n, treatment):
         _chk("lbm_batch_step", lib().lbm_batch_step(self._h, int(n), int(treatment)))
+
+    def step_residuals(self, treatment):
+        """(residuals, statuses) of every lattice after one batch step
+        (lbm_batch_step_residuals; inactive lattices: -1 and OK)."""
+        r = np.empty(self.count)
+        s = (ctypes.c_int * self.count)()
+        _chk("lbm_batch_step_residuals", lib().lbm_batch_step_residuals(self._h, int(treatment), _dp(r), s))
+        return r, list(s)
 
     def set_active(self, active=None):
         if active is None:

@@ -60,14 +60,12 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
         b.set_active(open_)
         b.step(chunk - 1, treatment)
         done += chunk
+        res, status = b.step_residuals(treatment)
         for i in range(n):
             if open_[i]:
-                try:
-                    r = b[i].step_residual(treatment)
-                except RuntimeError:
+                if status[i] != 0 or not np.isfinite(res[i]):
                     failed[i] = True
-                    continue
-                if r < target:
+                elif res[i] < target:
                     steps[i] = done
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

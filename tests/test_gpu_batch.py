@@ -113,6 +113,33 @@ def test_small_batch_one_row_tiles_bitwise(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+def test_batched_residuals_equal_member_residuals(precision):
+    """lbm_batch_step_residuals gives each active lattice the residual and
+    the state its own lbm_step_residual gives; inactive lattices are left
+    alone (-1, OK)."""
+    cases = _tiny_batch()
+    active = [True, False, True, True, False, True]
+    a, b = _batch(cases, precision), _batch(cases, precision)
+    for x in (a, b):
+        x.step(12, CORRECTED)
+        x.set_active(active)
+    for rep in range(3):
+        ra, sa = a.step_residuals(CORRECTED)
+        for i in range(len(cases)):
+            if active[i]:
+                rb = b[i].step_residual(CORRECTED)
+                assert ra[i] == rb and sa[i] == 0, (rep, i, ra[i], rb)
+            else:
+                assert ra[i] == -1.0 and sa[i] == 0
+        for i in range(len(cases)):
+            assert np.array_equal(a[i].get_state(), b[i].get_state()), (rep, i)
+        a.step(5, CORRECTED)
+        b.step(5, CORRECTED)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
 def test_batch_graph_replays_match_eager(precision):
     """Graph replays interleaved with eager steps and host syncs; every
     replay's result is checked against an eagerly stepped twin."""
