@@ -27,7 +27,7 @@ def _scalars(cases, Tc):
 
 
 def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=1000,
-          treatment=CORRECTED, graph=200, keep=True, physical=False):
+          treatment=CORRECTED, graph=50, keep=True, physical=False):
     """Run every case (a list of (params, rho, T)) from its initial fields
     (or from inits[i] = (rho, T) when given) to the residual target, in one
     batch with converged lattices frozen.  `physical` starts each lattice
