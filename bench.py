@@ -21,7 +21,12 @@ bytes per launch (`traffic`, from the profile summary while the kernel and
 tiling sources are unchanged) with the rate they imply (`measured_GBs`);
 `cpu_baseline` times the FP64 oracle on the host cores over a bounded
 number of steps of the same workload, and again on one core
-(`single_core`, a child process with one OpenMP thread).
+(`single_core`, a child process with one OpenMP thread).  Side sections:
+`by_precision` (FP64 and FP32 global-shift storage on the same slab),
+`batched` (256 uneven lattices stepped together, autotuned) and
+`steady_state` (wall time of held-out steady-state solves to a 1e-8
+residual: one lattice at a time, batched, warm-started, and started at
+rest in the forcing scheme's velocity).
 """
 import argparse
 import hashlib
