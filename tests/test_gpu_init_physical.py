@@ -161,3 +161,64 @@ def test_physical_start_shortens_steady_solves():
     say("restart steps zero momentum", ra["steps"], "physical", rb["steps"])
     assert all(s is not None for s in rb["steps"])
     assert tb < 0.5 * ta
+
+
+def _cavity_case(n=40):
+    """The natural-convection cavity of Sec. III.B (walls on all sides,
+    Dirichlet left and right, adiabatic top and bottom, ideal gas, mixed
+    force of Eq. (4) with beta = 0, gravity from Eq. (28)) started from
+    the conduction profile with a density ripple."""
+    # Ra = 100 keeps gravity (Eq. (28)) at 4e-4 on this small box; larger
+    # Ra at n = 40 drives the compressible LB model unstable
+    Th, Tl, mu, Pr, Ra = 1.03, 0.97, 0.1, 0.71, 1e2
+    g = Ra * mu ** 2 / ((1.0 / (0.5 * (Th + Tl))) * (Th - Tl) * n ** 3 * Pr)
+    p = dict(nx=n, ny=n, tau_f=0.5 + 3 * mu, tau_g=0.5 + 3 * mu / Pr, G=1.0, beta=0.0, eos="ideal",
+             R=1.0 / 3.0, cv=1.0, gx=0.0, gy=-g, wall_x=True, wall_y=True,
+             thermal_left="dirichlet", thermal_right="dirichlet", thermal_bottom="adiabatic",
+             thermal_top="adiabatic", T_left=Th, T_right=Tl, eos_fixed_T=False, T_eos=1.0)
+    x = (np.arange(n) + 0.5) / n
+    T = np.broadcast_to(Th + (Tl - Th) * x[None, :], (n, n)).copy()
+    rho = 1.0 + 0.01 * np.sin(2 * np.pi * x)[None, :] * np.cos(np.pi * x)[:, None]
+    return p, rho, T
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+def test_cavity_physical_start(precision):
+    """Walls on every side and the finite-difference treatment (Eq. (26))
+    after the physical start, against the oracle."""
+    from oracle import FD_RK2
+    from paper_1405_2232_amd.lbm import Lattice
+    say("case cavity physical start", precision)
+    p, rho, T = _cavity_case()
+    o = Oracle(p)
+    o.init_fields_physical(rho, T)
+    fo, go = o.get_state()
+    ref = np.concatenate([fo, go])
+    g = Lattice(p, precision)
+    g.init_fields(rho, T, physical=True)
+    err = np.abs(g.get_state() - ref).max() / np.abs(ref).max()
+    _, u, v, _ = g.moments()
+    eu = max(np.abs(u).max(), np.abs(v).max())
+    g.init_fields(rho, T)
+    _, u0, v0, _ = g.moments()
+    off = max(np.abs(u0).max(), np.abs(v0).max())
+    say("state rel err", err, "velocity", eu, "plain start velocity", off)
+    assert off > 1e-5  # the force is small here, but not zero
+    if precision == "fp64":
+        assert err < 1e-14 and eu < 1e-15
+    else:
+        assert err < 1e-6 and eu < 1e-7
+    g.close()
+    if precision != "fp64":
+        return
+    for treatment in (CORRECTED, FD_RK2):
+        o = Oracle(p)
+        o.init_fields_physical(rho, T)
+        assert o.step(150, treatment) == 0
+        g = Lattice(p, "fp64")
+        g.init_fields(rho, T, physical=True)
+        g.step(150, treatment)
+        errs = [np.abs(a - b).max() for a, b in zip(g.moments(), o.moments())]
+        say("cavity fp64 after 150 steps", treatment, errs)
+        assert max(errs) < FP64_TOL
+        g.close()
