@@ -412,6 +412,19 @@ def main():
                 and tr.get("steps_per_launch", 1) == per_launch:
             traffic = tr.get("bytes_per_launch")
 
+    # the same K steps with the boundary's host transfers timed in: FP64
+    # host fields in (lbm_init_fields), K steps, FP64 host moments out
+    # (lbm_moments); never `value`, whose state is resident in HBM
+    g.set_check_interval(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.init_fields(rho, T)
+    g.step(args.steps, treatment)
+    g.moments()
+    wall_h = time.perf_counter() - t0
+    host_inclusive = {"mlups": round(cells * args.steps / wall_h / 1e6, 1), "ms": round(wall_h * 1e3, 2),
+                      "what": "host rho, T in; %d steps; host rho, u, T out" % args.steps}
+
     copy_ms, copy_gbs = copy_rate(1 << 30)
 
     extra = {}
@@ -460,6 +473,7 @@ def main():
                                       if traffic else None),
                      "copy_GBs": round(copy_gbs, 1)},
         "by_precision": extra,
+        "host_inclusive": host_inclusive,
     }
     if not args.no_batch:
         line["batched"] = batch_section(args.batch_steps, torch)
