@@ -16,14 +16,19 @@ Prints one JSON line.  `value` is MLUPS (lattice updates per second / 1e6)
 with the state resident in HBM.  `roofline` prices the dominant kernel's
 algorithmic bytes (18 distributions read + written per node and step, 144
 B in FP32, times the steps per launch) against the 8 TB/s HBM peak, gives
-the launch time measured with HIP events, and the counter-measured HBM
+the launch time measured with HIP events on the launch stream (its own
+100-step warm-up, then the median of five runs of 200 launches, with their
+min and max, whatever --steps is; this leg runs first, so the timed region
+also starts on a warm device), and the counter-measured HBM
 bytes per launch (`traffic`, from the profile summary while the kernel and
 tiling sources are unchanged) with the rate they imply (`measured_GBs`);
 `cpu_baseline` times the FP64 oracle on the host cores over a bounded
 number of steps of the same workload, and again on one core
 (`single_core`, a child process with one OpenMP thread).  Side sections:
-`by_precision` (FP64 and FP32 global-shift storage on the same slab),
-`batched` (256 uneven lattices stepped together, autotuned) and
+`by_precision` (FP64 and FP32 global-shift storage on the same slab,
+timed like the roofline leg), `batched` (256 uneven lattices stepped
+together, autotuned, against the same lattices one at a time in the same
+storage form and in FP64) and
 `steady_state` (wall time of held-out steady-state solves to a 1e-8
 residual: one lattice at a time, batched, warm-started, and started at
 rest in the forcing scheme's velocity).
@@ -168,8 +173,9 @@ def batch_section(steps, torch):
     replayed from hipGraphs, FP32 per-node-reference storage, autotuned
     band height (the one-step tile shape is tuned too; it serves odd steps);
     against the same lattices advanced one after another by single-lattice
-    FP64 launches (timed over fewer steps per lattice and scaled: the cost
-    per step is constant)."""
+    launches, in the same storage form (the gain of batching alone) and in
+    FP64 (timed over fewer steps per lattice and scaled: the cost per step
+    is constant)."""
     from paper_1405_2232_amd import autotune, inputs
     from paper_1405_2232_amd.lbm import CORRECTED, Batch, Lattice
     cases = inputs.batch_lattices()
@@ -206,24 +212,33 @@ def batch_section(steps, torch):
     batch_ms = e0.elapsed_time(e1)
     del b
 
-    seq_steps = 100
-    seq_ms = 0.0
-    for (p, rho, T) in cases:
-        g = Lattice(p, "fp64")
-        g.init_fields(rho, T)
-        g.step(10, CORRECTED)
-        seq_ms += timed_steps(g, seq_steps, CORRECTED, torch) * steps
-        del g
+    # the same lattices one after another, single-lattice launches, in the
+    # batch's storage form (the batching gain alone) and in FP64
+    seq_steps = 500
+    seq = {}
+    for prec in ("fp32local", "fp64"):
+        seq_ms = 0.0
+        for (p, rho, T), ref in zip(cases, refs):
+            g = Lattice(p, prec, rho_ref=ref[0], T_ref=ref[1]) if prec != "fp64" else Lattice(p, prec)
+            g.init_fields(rho, T)
+            g.step(10, CORRECTED)
+            seq_ms += timed_steps(g, seq_steps, CORRECTED, torch) * steps
+            del g
+        seq[prec] = seq_ms
     return {"lattices": len(cases), "nodes": cells, "steps": steps,
             "fp32local_graph_s": round(batch_ms / 1e3, 3), "wall_s": round(wall, 3),
             "mlups": round(cells * steps / (batch_ms / 1e3) / 1e6, 1),
+            "alg_GBs": round(ALG_BYTES["fp32local"] * cells * steps / (batch_ms / 1e3) / 1e9, 1),
             "tile": [bx, rows], "autotune_ms_per_step": tried,
             "pair_rows": prows, "autotune_pair_ms_per_step": ptried,
-            "sequential_fp64_s": round(seq_ms / 1e3, 3),
-            "sequential_fp64_mlups": round(cells * steps / (seq_ms / 1e3) / 1e6, 1),
-            "speedup": round(seq_ms / batch_ms, 2),
-            "sequential_note": "single-lattice FP64 launches, %d timed steps per lattice, scaled to %d"
-                               % (seq_steps, steps)}
+            "sequential_fp32local_s": round(seq["fp32local"] / 1e3, 3),
+            "sequential_fp32local_mlups": round(cells * steps / (seq["fp32local"] / 1e3) / 1e6, 1),
+            "speedup_same_storage": round(seq["fp32local"] / batch_ms, 2),
+            "sequential_fp64_s": round(seq["fp64"] / 1e3, 3),
+            "sequential_fp64_mlups": round(cells * steps / (seq["fp64"] / 1e3) / 1e6, 1),
+            "speedup_vs_fp64": round(seq["fp64"] / batch_ms, 2),
+            "sequential_note": "single-lattice launches, %d timed steps per lattice (after 10), "
+                               "scaled to %d: the cost per step is constant" % (seq_steps, steps)}
 
 
 def timed_steps(g, steps, treatment, torch):
@@ -237,6 +252,20 @@ def timed_steps(g, steps, treatment, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def kernel_timing(g, treatment, torch, warm=100, runs=5, launches=200):
+    """Launch time of the step kernel alone: `warm` untimed steps, then
+    `runs` runs of `launches` launches each, every run bracketed by HIP
+    events on the launch stream (torch's current stream; no periodic check
+    inside).  Returns the median, min and max ms per launch and the steps
+    one launch advances."""
+    g.set_check_interval(0)
+    per = 2 if g.get_step_pairing()[0] else 1
+    g.step(warm + (warm & 1), treatment)
+    times = sorted(timed_steps(g, launches * per, treatment, torch) * per for _ in range(runs))
+    return {"median": times[runs // 2], "min": times[0], "max": times[-1],
+            "steps_per_launch": per, "runs": runs, "launches": launches, "warmup": warm}
 
 
 def cpu_baseline(p, rho, T, treatment, seconds):
@@ -375,6 +404,17 @@ def main():
     g.init_fields(rho, T)
     if args.no_pair:
         g.set_step_pairing(False)
+
+    # step kernel alone (the roofline): its own warm-up, then the median of
+    # five event-timed runs, whatever --steps and --warmup are; this also
+    # brings the device to its working clocks before the timed region
+    kt = kernel_timing(g, treatment, torch)
+    per_launch = kt["steps_per_launch"]
+    paired = per_launch == 2
+    launch_ms = kt["median"]
+    kernel_ms = launch_ms / per_launch
+    achieved = ALG_BYTES[args.precision] * cells * per_launch / (launch_ms * 1e-3) / 1e9
+
     g.set_check_interval(100)
     if args.warmup > 0:
         g.step(args.warmup, treatment)
@@ -392,16 +432,6 @@ def main():
         raise SystemExit("the run reported status %d" % status)
     ms_per_step = wall * 1e3 / args.steps
     mlups = cells * args.steps / wall / 1e6
-
-    # step kernel alone, HIP events on the launch stream; with step pairing
-    # one launch advances two steps (an even step count: every launch pairs)
-    g.set_check_interval(0)
-    paired = g.get_step_pairing()[0]
-    per_launch = 2 if paired else 1
-    k_steps = 2 * (min(500, max(50, args.steps // 4)) // 2)
-    kernel_ms = timed_steps(g, k_steps, treatment, torch)
-    launch_ms = kernel_ms * per_launch
-    achieved = ALG_BYTES[args.precision] * cells * per_launch / (launch_ms * 1e-3) / 1e9
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -424,6 +454,7 @@ def main():
     wall_h = time.perf_counter() - t0
     host_inclusive = {"mlups": round(cells * args.steps / wall_h / 1e6, 1), "ms": round(wall_h * 1e3, 2),
                       "what": "host rho, T in; %d steps; host rho, u, T out" % args.steps}
+    del g
 
     copy_ms, copy_gbs = copy_rate(1 << 30)
 
@@ -434,13 +465,19 @@ def main():
                 continue
             h = Lattice(p, prec)
             h.init_fields(rho, T)
-            h.step(50, treatment)
-            ms = timed_steps(h, 200, treatment, torch)
+            if args.no_pair:
+                h.set_step_pairing(False)
+            ht = kernel_timing(h, treatment, torch)
+            ms = ht["median"] / ht["steps_per_launch"]
             extra[prec] = {"mlups": round(cells / ms / 1e3, 1),
-                           "alg_GBs": round(ALG_BYTES[prec] * cells / ms / 1e6, 1)}
+                           "alg_GBs": round(ALG_BYTES[prec] * cells / ms / 1e6, 1),
+                           "launch_ms": [round(ht[k], 5) for k in ("median", "min", "max")],
+                           "steps_per_launch": ht["steps_per_launch"]}
             del h
         extra[args.precision] = {"mlups": round(cells / kernel_ms / 1e3, 1),
-                                 "alg_GBs": round(achieved, 1)}
+                                 "alg_GBs": round(achieved, 1),
+                                 "launch_ms": [round(kt[k], 5) for k in ("median", "min", "max")],
+                                 "steps_per_launch": per_launch}
 
     line = {
         "metric": "MLUPS (FP64 vs FP32-dev, % HBM roofline); wall-time to 1e-8 residual vs plain",
@@ -467,6 +504,9 @@ def main():
                      "kernel": "k_pair" if paired else "k_tile",
                      "steps_per_launch": per_launch,
                      "launch_ms": round(launch_ms, 5),
+                     "launch_ms_min_max": [round(kt["min"], 5), round(kt["max"], 5)],
+                     "timing": "median of %d runs of %d launches after %d warm-up steps, HIP events"
+                               % (kt["runs"], kt["launches"], kt["warmup"]),
                      "kernel_ms": round(kernel_ms, 5),
                      "bytes_per_node": ALG_BYTES[args.precision],
                      "measured_GBs": (round(traffic / (launch_ms * 1e-3) / 1e9, 1)

@@ -3,7 +3,8 @@
 Times a few candidate tile shapes (lanes per block, rows per band) of the
 one-step kernel, or band heights of the two-step kernel, on a scratch copy
 of the work (a lattice or a batch built by `make`, so the caller's state is
-not advanced) and keeps the fastest.  Results are cached
+not advanced; each candidate is timed three times and its median kept)
+and keeps the fastest.  Results are cached
 in a JSON file keyed by the device name, the storage form and the lattice
 sizes, so a later run of the same shape of work skips the timing.
 """
@@ -44,17 +45,22 @@ def _store(cache):
         pass
 
 
-def _time(obj, steps, treatment):
+def _time(obj, steps, treatment, repeats=3):
+    """Median over `repeats` event-timed runs of `steps` steps (after two
+    untimed ones): ms per step."""
     import torch
     obj.step(2, treatment)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    obj.step(steps, treatment)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        e0.record()
+        obj.step(steps, treatment)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    return sorted(times)[repeats // 2]
 
 
 def tune(make, kind, precision, sizes, treatment=1, steps=20, candidates=CANDIDATES, use_cache=True):
