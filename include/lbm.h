@@ -111,7 +111,12 @@ typedef struct {
                         /* LBM_THERMAL_DIRICHLET: g anti-bounces back
                            with the wall value rho cv T_w; ADIABATIC: g
                            bounces back.  Where a diagonal leaves through
-                           a corner the y wall's condition applies. */
+                           a corner of a box (wall_x = 1) it meets both
+                           walls: adiabatic if either is, else Dirichlet
+                           at the mean of the two wall temperatures (the
+                           scheme stays covariant under exchanging x and
+                           y); at a corner of the open channel the plate's
+                           condition applies. */
   double T_left, T_right, T_bottom, T_top;
   int psi_policy;       /* 0: psi^2 < 0 clamps psi to 0 and is counted;
                            1: the same, and lbm_sync()/lbm_moments()

@@ -67,8 +67,10 @@
  *   - walls sit halfway between nodes; f bounces back; g bounces back
  *     (adiabatic) or anti-bounces back with the wall value rho(x) cv T_w
  *     (Dirichlet); the pseudopotential ghost beyond a wall mirrors the
- *     boundary node.  Where a diagonal leaves through a corner, the
- *     y-wall's thermal condition applies.
+ *     boundary node.  Where a diagonal leaves through a corner of a box,
+ *     the corner is adiabatic if either wall is, else Dirichlet at the
+ *     mean of the two wall temperatures (no axis preferred); at a corner
+ *     of the open channel the plate's condition applies.
  */
 #include "lbmref.h"
 
@@ -154,6 +156,28 @@ double lbmref_pressure(const lbmref_params *p, double rho, double T) {
   double num = 1.0 + eta + eta * eta - eta * eta * eta;
   double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);
   return rho * p->R * T * num / den - p->a * rho * rho;
+}
+
+/* thermal condition beyond a wall of a box: side 0 left, 1 right, 2 bottom,
+ * 3 top, -1 where that axis is not crossed.  Where both are crossed (a
+ * diagonal leaving through a corner, or a ghost node beyond one), the
+ * corner is adiabatic if either wall is, else Dirichlet at the mean of the
+ * two wall temperatures: no axis is preferred, so the scheme stays
+ * covariant under the exchange of x and y (the walls are a reading: the
+ * paper's benchmarks state only which sides hold which condition).
+ * Returns the condition and sets *Tw. */
+static int wall_condition(const lbmref_params *p, int sx, int sy, double *Tw) {
+  const int th[4] = {p->thermal_left, p->thermal_right, p->thermal_bottom, p->thermal_top};
+  const double tw[4] = {p->T_left, p->T_right, p->T_bottom, p->T_top};
+  if (sx >= 0 && sy >= 0) {
+    *Tw = 0.5 * (tw[sx] + tw[sy]);
+    if (th[sx] == LBMREF_THERMAL_ADIABATIC || th[sy] == LBMREF_THERMAL_ADIABATIC)
+      return LBMREF_THERMAL_ADIABATIC;
+    return LBMREF_THERMAL_DIRICHLET;
+  }
+  const int s = sx >= 0 ? sx : sy;
+  *Tw = tw[s];
+  return th[s];
 }
 
 /* neighbour index with periodic wrap or wall mirror; returns the node
@@ -372,15 +396,11 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
         }
         if (hit_y || hit_x) {
           int o = opposite(i);
-          int thermal;
+          /* at a corner of the open channel the plate's condition applies */
+          int sx = hit_x && !open ? (xn < 0 ? 0 : 1) : -1;
+          int sy = hit_y ? (yn < 0 ? 2 : 3) : -1;
           double Tw;
-          if (hit_y) {
-            thermal = yn < 0 ? p->thermal_bottom : p->thermal_top;
-            Tw = yn < 0 ? p->T_bottom : p->T_top;
-          } else {
-            thermal = xn < 0 ? p->thermal_left : p->thermal_right;
-            Tw = xn < 0 ? p->T_left : p->T_right;
-          }
+          int thermal = wall_condition(p, sx, sy, &Tw);
           h->f2[PL(h, o) + c] = fs;
           if (thermal == LBMREF_THERMAL_DIRICHLET)
             h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * p->cv * r * Tw;
@@ -412,18 +432,13 @@ static double ghost(lbmref_handle h, const double *phi, int x, int y, int is_T) 
   if (outy) ym = p->wall_y ? (y < 0 ? 0 : ny - 1) : (y < 0 ? y + ny : y - ny);
   double v = phi[IDX(h, xm, ym)];
   if (!is_T) return v;
-  /* the y wall's condition applies where both are crossed (corners) */
-  if (outy && p->wall_y) {
-    int th = y < 0 ? p->thermal_bottom : p->thermal_top;
-    double Tw = y < 0 ? p->T_bottom : p->T_top;
-    return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;
-  }
-  if (outx && p->wall_x) {
-    int th = x < 0 ? p->thermal_left : p->thermal_right;
-    double Tw = x < 0 ? p->T_left : p->T_right;
-    return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;
-  }
-  return v;
+  int sx = outx && p->wall_x ? (x < 0 ? 0 : 1) : -1;
+  int sy = outy && p->wall_y ? (y < 0 ? 2 : 3) : -1;
+  if (p->wall_x == 2 && sy >= 0) sx = -1; /* open channel: the plate's condition at corners */
+  if (sx < 0 && sy < 0) return v;
+  double Tw;
+  int th = wall_condition(p, sx, sy, &Tw);
+  return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;
 }
 
 /* (dp_EOS/dT) at fixed rho: Carnahan-Starling rho R Z(eta), ideal rho R */

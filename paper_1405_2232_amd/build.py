@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_device.hip", "lbm_api.hip", "lbm_batch.hip", "lbm_init.hip", "nn_device.hip", "nn_api.hip"]
+SOURCES = ["lbm_device.hip", "lbm_api.hip", "lbm_batch.hip", "lbm_init.hip",
+           "nn_device.hip", "nn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -19,7 +20,10 @@ FLAGS = [
 
 
 def build(verbose=False, extra=None):
-    objs = []
+    """Compile every source (in parallel, one hipcc per file) and link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    jobs = []
     for src in SOURCES:
         s = os.path.join(CSRC, src)
         if not os.path.exists(s):
@@ -28,8 +32,12 @@ def build(verbose=False, extra=None):
         cmd = [HIPCC] + FLAGS + (extra or []) + ["-I", os.path.join(ROOT, "include"), "-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(o)
+        jobs.append((cmd, o))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(subprocess.check_call, cmd) for cmd, _ in jobs]:
+            f.result()
+    objs = [o for _, o in jobs]
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -456,13 +456,19 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         C fo, go, fs, gs;
         post_to(i, rd, fo, go);
         P.raw(i, (C)d.v[i], (C)d.v[9 + i], fs, gs);
-        // halfway bounce-back into the same node; the y wall wins at corners;
-        // Dirichlet walls anti-bounce-back with the wall value rho cv T_w
+        // halfway bounce-back into the same node; Dirichlet walls
+        // anti-bounce-back with the wall value rho cv T_w.  A diagonal
+        // leaving through a corner of a box meets both walls: adiabatic if
+        // either is, else Dirichlet at the mean wall temperature (no axis
+        // preferred); at a corner of the open channel the plate's rule holds
         const bool hy = row < 0;
-        const int th = hy ? (eyi < 0 ? m.thermal[2] : m.thermal[3])
-                          : (exi < 0 ? m.thermal[0] : m.thermal[1]);
-        const double wE = hy ? (eyi < 0 ? m.wall_E[2] : m.wall_E[3])
-                             : (exi < 0 ? m.wall_E[0] : m.wall_E[1]);
+        const int ky = eyi < 0 ? 2 : 3, kx = exi < 0 ? 0 : 1;
+        int th = hy ? m.thermal[ky] : m.thermal[kx];
+        double wE = hy ? m.wall_E[ky] : m.wall_E[kx];
+        if (hy && col < 0 && m.wall_x == 1) {
+          th = (m.thermal[kx] != 0 || m.thermal[ky] != 0) ? 1 : 0;
+          wE = 0.5 * (m.wall_E[kx] + m.wall_E[ky]);
+        }
         const double refE = ST == ST_F64 ? 0.0
                             : (ST == ST_F32_GLOBAL ? m.rho_ref * m.cvT_ref
                                                    : (double)rb_old * m.cvT_ref);
@@ -1142,17 +1148,20 @@ __device__ inline long long fd_node(const Model &m, int x, int y, bool &ox, bool
 }
 
 // temperature ghost beyond a wall (halfway): 2 T_w - T(mirror) for a
-// Dirichlet wall, T(mirror) for an adiabatic one; the y wall rules corners
+// Dirichlet wall, T(mirror) for an adiabatic one.  Beyond a corner of a box
+// (both walls crossed) the corner is adiabatic if either wall is, else
+// Dirichlet at the mean of the two wall temperatures, so that neither axis
+// is preferred; at a corner of the open channel the plate's condition holds.
 __device__ inline double fd_T_ghost(const Model &m, double v, int x, int y, bool ox, bool oy) {
-  if (oy && m.wall_y) {
-    const int k = y < 0 ? 2 : 3;
-    return m.thermal[k] == 0 ? 2.0 * m.T_wall[k] - v : v;
+  const int kx = (ox && m.wall_x) ? (x < 0 ? 0 : 1) : -1;
+  const int ky = (oy && m.wall_y) ? (y < 0 ? 2 : 3) : -1;
+  if (ky >= 0 && kx >= 0 && m.wall_x == 1) {
+    if (m.thermal[kx] != 0 || m.thermal[ky] != 0) return v;
+    return 2.0 * (0.5 * (m.T_wall[kx] + m.T_wall[ky])) - v;
   }
-  if (ox && m.wall_x) {
-    const int k = x < 0 ? 0 : 1;
-    return m.thermal[k] == 0 ? 2.0 * m.T_wall[k] - v : v;
-  }
-  return v;
+  const int k = ky >= 0 ? ky : kx;
+  if (k < 0) return v;
+  return m.thermal[k] == 0 ? 2.0 * m.T_wall[k] - v : v;
 }
 
 // (dp_EOS/dT) at fixed rho: Carnahan-Starling rho R Z(eta), ideal rho R

@@ -16,10 +16,24 @@ import oracle.lbmref as _ref
 import test_oracle_channel as channel
 import test_oracle_fd as fd
 import test_oracle_pins as pins
+import test_oracle_walls as walls
 
 
 def _channel_poiseuille():
     channel.test_poiseuille_flux_outlet_density_and_profile()
+
+
+def _case_a_inlet():
+    walls.test_inlet_holds_the_inflow_temperature(walls._steady(walls._channel(120, 20, 1.03, 0.97), 1.0, 30000))
+
+
+def _case_a_outlet():
+    walls.test_outlet_carries_the_channel_temperature_out(
+        walls._steady(walls._channel(120, 20, 1.03, 0.97), 1.0, 30000))
+
+
+def _covariance(walls_index, treatment):
+    return lambda: walls.test_walled_box_is_covariant_under_exchange_of_x_and_y(walls_index, treatment)
 
 SRC = os.path.join(os.path.dirname(_build.__file__), "lbmref.c")
 HDR = os.path.join(os.path.dirname(_build.__file__), "lbmref.h")
@@ -136,9 +150,38 @@ MUTATIONS = [
      "K[c] += phi * du / (h->rho[c] * p->cv);", "K[c] -= phi * du / (h->rho[c] * p->cv);",
      [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0)]),
     ("finite-difference Dirichlet ghost equal to the wall value",
-     "return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;\n  }\n  if (outx && p->wall_x) {",
-     "return th == LBMREF_THERMAL_DIRICHLET ? Tw : v;\n  }\n  if (outx && p->wall_x) {",
+     "int th = wall_condition(p, sx, sy, &Tw);\n  return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;",
+     "int th = wall_condition(p, sx, sy, &Tw);\n  return th == LBMREF_THERMAL_DIRICHLET ? Tw : v;",
      [lambda: fd.test_linear_conduction_is_a_fixed_point_and_the_limit(0.6)]),
+    ("inlet g equilibrium without its velocity terms",
+     "(1.0 + 4.5 * eu * eu - 1.5 * p->u_in * p->u_in);", "1.0;",
+     [_case_a_inlet]),
+    ("inlet g bounces back",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * p->cv * r * p->T_left *",
+     "h->g2[PL(h, o) + c] = gs + 0.0 * W[i] * p->cv * r * p->T_left *",
+     [lambda: walls.test_isothermal_channel_stays_at_its_temperature(1)]),
+    ("outlet g holds the inflow temperature",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * cvT * r * even;",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * p->cv * p->T_left * r * even;",
+     [_case_a_outlet]),
+    ("outlet g bounces back",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * cvT * r * even;",
+     "h->g2[PL(h, o) + c] = gs;",
+     [walls.test_adiabatic_channel_fills_with_the_inflow_temperature]),
+    ("outlet g equilibrium without its velocity terms",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * cvT * r * even;",
+     "h->g2[PL(h, o) + c] = -gs + 2.0 * W[i] * cvT * r;",
+     [lambda: walls.test_isothermal_channel_stays_at_its_temperature(1)]),
+    ("the y wall wins at box corners",
+     "int sx = hit_x && !open ? (xn < 0 ? 0 : 1) : -1;",
+     "int sx = hit_x && !open && !hit_y ? (xn < 0 ? 0 : 1) : -1;",
+     [_covariance(1, 1), _covariance(2, 1)]),
+    ("a Dirichlet corner takes one wall's temperature",
+     "*Tw = 0.5 * (tw[sx] + tw[sy]);", "*Tw = tw[sy];",
+     [_covariance(0, 1)]),
+    ("finite-difference ghost: the y wall wins at box corners",
+     "if (p->wall_x == 2 && sy >= 0) sx = -1;", "if (sy >= 0) sx = -1;",
+     [_covariance(0, 2), _covariance(2, 2)]),
 ]
 
 
