@@ -190,6 +190,20 @@ int lbm_moments_device(lbm_handle h, double *d_rho, double *d_ux, double *d_uy, 
  * taken, out[7] 0.  Synchronizes. */
 int lbm_totals(lbm_handle h, double out[8]);
 
+/* lbm_totals for callers that cannot allocate device memory around the
+ * call (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  The same totals, bit for bit, from the same kernels;
+ * their scratch memory (per-block FP64 partial sums and the reduced
+ * totals) lives in a static device array of the library, 2.6 MB on each
+ * GPU the library runs on, held until the process ends, instead of in the
+ * handle's workspace.  A lattice whose moments launch needs more than
+ * 32768 blocks (beyond about 5,800^2 nodes) gives LBM_EINVAL; an
+ * uninitialised handle LBM_ESTATE.  Every call on one GPU uses that GPU's
+ * one array: calls that overlap on one GPU (from other threads, on other
+ * streams) race, and the caller must serialize them.  Synchronizes the
+ * handle's stream. */
+int lbm_totals_noalloc(lbm_handle h, double out[8]);
+
 /* Relative change of rho and T over one step,
  * max over {rho, T} of ||phi^n - phi^(n-1)||_inf / ||phi^n||_inf.
  * Takes one step with `treatment`.  Synchronizes. */

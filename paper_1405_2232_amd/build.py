@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_device.hip", "lbm_api.hip", "lbm_batch.hip", "lbm_init.hip",
+SOURCES = ["lbm_device.hip", "lbm_api.hip", "lbm_batch.hip", "lbm_init.hip", "lbm_noalloc.hip",
            "nn_device.hip", "nn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -82,6 +82,7 @@ def lib():
             "lbm_moments": [vp, dp, dp, dp, dp],
             "lbm_moments_device": [vp, vp, vp, vp, vp],
             "lbm_totals": [vp, dp],
+            "lbm_totals_noalloc": [vp, dp],
             "lbm_step_residual": [vp, i, dp],
             "lbm_get_state": [vp, dp],
             "lbm_set_state": [vp, dp],
@@ -221,6 +222,13 @@ class _HandleOps:
     def totals(self):
         out = np.zeros(8)
         _chk("lbm_totals", lib().lbm_totals(self._h, _dp(out)))
+        return out
+
+    def totals_noalloc(self):
+        """lbm_totals_noalloc: the same totals with the library's static
+        scratch array (no workspace scratch)."""
+        out = np.zeros(8)
+        _chk("lbm_totals_noalloc", lib().lbm_totals_noalloc(self._h, _dp(out)))
         return out
 
     def step_residual(self, treatment):
