@@ -47,11 +47,13 @@
  *     Eq. (23)); u and rho are those of time t for both stages.  Beyond a
  *     Dirichlet wall the temperature ghost is 2 T_w - T(boundary node),
  *     beyond an adiabatic wall T(boundary node); rho mirrors;
- *   - with phi_divu the finite-difference treatment keeps the term
- *     phi div u of Eq. (5), phi = -T (dp_EOS/dT)_rho, in K(T) as
- *     phi div u / (rho cv), div u by the same isotropic gradient (the
- *     velocity ghost beyond a wall is the boundary node's velocity
- *     reversed, for a no-slip wall halfway out);
+ *   - with phi_divu the term phi div u of Eq. (5), phi = -T (dp_EOS/dT)_rho,
+ *     which the paper omits (Eq. (6)), is kept: the finite-difference
+ *     treatment adds phi div u / (rho cv) to K(T); the LB treatments add
+ *     the source w_i phi div u to g_i* (zeroth moment phi div u, first and
+ *     second moments zero; u of time t); div u by the same isotropic
+ *     gradient (the velocity ghost beyond a wall is the boundary node's
+ *     velocity reversed, for a no-slip wall halfway out);
  *   - open channel (wall_x = 2; the paper states inlet and outlet only as
  *     uniform inflow and fully developed outflow): the inlet sits halfway
  *     left of the first column, where f bounces back with the momentum of
@@ -345,11 +347,23 @@ static void total_force(lbmref_handle h, double *Fx, double *Fy) {
   }
 }
 
-/* pass 2: collide (Eq. (1) and Eq. (7) or Eq. (24)) and stream */
+static double phi_divu_at(lbmref_handle h, const double *T, int x, int y);
+
+/* pass 2: collide (Eq. (1) and Eq. (7) or Eq. (24)) and stream.  With
+ * phi_divu the LB g update also takes the source term of Eq. (5), whose
+ * paper omits it (Eq. (6)): g_i* += w_i phi div u (dt = 1), the velocity
+ * of time t; its divergence needs every node's velocity first. */
 static void pass_collide_stream(lbmref_handle h, const double *Fx, const double *Fy,
                                 int treatment) {
   const lbmref_params *p = &h->p;
   const int nx = p->nx, ny = p->ny;
+  const int src = p->phi_divu && treatment != LBMREF_FD_RK2;
+  if (src) {
+    for (long c = 0; c < h->n; ++c) {
+      h->ux[c] = (h->jx[c] + 0.5 * Fx[c]) / h->rho[c];
+      h->uy[c] = (h->jy[c] + 0.5 * Fy[c]) / h->rho[c];
+    }
+  }
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
@@ -357,8 +371,11 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
       double r = h->rho[c];
       double ux = (h->jx[c] + 0.5 * Fx[c]) / r;
       double uy = (h->jy[c] + 0.5 * Fy[c]) / r;
-      h->ux[c] = ux;
-      h->uy[c] = uy;
+      if (!src) {
+        h->ux[c] = ux;
+        h->uy[c] = uy;
+      }
+      const double S = src ? phi_divu_at(h, h->T, x, y) : 0.0;
       double cvT = p->cv * h->T[c];
       double feq[9], fi_force[9], ci[9];
       lbmref_feq(r, ux, uy, feq);
@@ -371,6 +388,7 @@ static void pass_collide_stream(lbmref_handle h, const double *Fx, const double 
         double geq = cvT * feq[i];
         double gs = gi - (gi - geq) / p->tau_g;
         if (treatment == LBMREF_CORRECTED) gs += ci[i];
+        if (src) gs += W[i] * S;
 
         int xn = x + EX[i], yn = y + EY[i];
         int out_x = (xn < 0 || xn >= nx), out_y = (yn < 0 || yn >= ny);
@@ -460,6 +478,22 @@ static double u_ghost(lbmref_handle h, const double *u, int x, int y) {
   return v;
 }
 
+/* phi div u of Eq. (5) at node (x, y): phi = -T (dp_EOS/dT)_rho with the
+ * node's T and rho, div u by the isotropic central difference
+ * sum_i w(|e_i|^2) u(x + e_i) . e_i of the velocities in h->ux, h->uy */
+static double phi_divu_at(lbmref_handle h, const double *T, int x, int y) {
+  const lbmref_params *p = &h->p;
+  long c = IDX(h, x, y);
+  double du = 0.0;
+  for (int i = 1; i < 9; ++i) {
+    double w = w_sc(i);
+    du += w * (u_ghost(h, h->ux, x + EX[i], y + EY[i]) * EX[i] +
+               u_ghost(h, h->uy, x + EX[i], y + EY[i]) * EY[i]);
+  }
+  double phi = -T[c] * dp_dT(p, h->rho[c]);
+  return phi * du;
+}
+
 /* K(T) of Eq. (26) at every node, with u and rho of time t */
 static void fd_rhs(lbmref_handle h, const double *T, double *K) {
   const lbmref_params *p = &h->p;
@@ -482,16 +516,7 @@ static void fd_rhs(lbmref_handle h, const double *T, double *K) {
       double lam = lam_per_rho * h->rho[c];
       double div = lam * lapT + gLx * gTx + gLy * gTy;
       K[c] = -(h->ux[c] * gTx + h->uy[c] * gTy) + div / (h->rho[c] * p->cv);
-      if (p->phi_divu) {
-        double du = 0.0;
-        for (int i = 1; i < 9; ++i) {
-          double w = w_sc(i);
-          du += w * (u_ghost(h, h->ux, x + EX[i], y + EY[i]) * EX[i] +
-                     u_ghost(h, h->uy, x + EX[i], y + EY[i]) * EY[i]);
-        }
-        double phi = -T[c] * dp_dT(p, h->rho[c]);
-        K[c] += phi * du / (h->rho[c] * p->cv);
-      }
+      if (p->phi_divu) K[c] += phi_divu_at(h, T, x, y) / (h->rho[c] * p->cv);
     }
   }
 }

@@ -44,8 +44,9 @@ typedef struct {
   int psi_policy;           /* 0 clamp psi to 0 and count, 1 also flag an error */
   double u_in;              /* inlet velocity (wall_x = 2) */
   double rho_out;           /* outlet density (wall_x = 2) */
-  int phi_divu;             /* 1: the finite-difference treatment keeps the
-                               phi div u term of Eq. (5) */
+  int phi_divu;             /* 1: keep the phi div u term of Eq. (5): in K(T)
+                               for the finite-difference treatment, as the
+                               source w_i phi div u of g_i* for the LB ones */
 } lbmref_params;
 
 typedef struct lbmref_ctx *lbmref_handle;

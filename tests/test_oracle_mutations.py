@@ -147,8 +147,15 @@ MUTATIONS = [
      "h->f2[PL(h, o) + c] = fs + 2.0 * W[i] * p->rho_out * even;",
      [_channel_poiseuille]),
     ("phi div u with the wrong sign",
-     "K[c] += phi * du / (h->rho[c] * p->cv);", "K[c] -= phi * du / (h->rho[c] * p->cv);",
-     [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0)]),
+     "  return phi * du;\n}", "  return -phi * du;\n}",
+     [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0, 2)]),
+    ("LB source phi div u without its weights",
+     "if (src) gs += W[i] * S;", "if (src) gs += S;",
+     [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0, 1)]),
+    ("LB source phi div u left out of the plain treatment",
+     "const int src = p->phi_divu && treatment != LBMREF_FD_RK2;",
+     "const int src = p->phi_divu && treatment == LBMREF_CORRECTED;",
+     [lambda: fd.test_phi_divu_gives_the_adiabatic_temperature_of_a_sound_wave(1.0, 0)]),
     ("finite-difference Dirichlet ghost equal to the wall value",
      "int th = wall_condition(p, sx, sy, &Tw);\n  return th == LBMREF_THERMAL_DIRICHLET ? 2.0 * Tw - v : v;",
      "int th = wall_condition(p, sx, sy, &Tw);\n  return th == LBMREF_THERMAL_DIRICHLET ? Tw : v;",
