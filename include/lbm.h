@@ -126,10 +126,14 @@ typedef struct {
                            T_ref for both FP32 forms */
   double u_in, rho_out; /* open channel (wall_x = 2): inlet velocity and
                            outlet density (> 0) */
-  int phi_divu;         /* 1: LBM_FD_RK2 keeps the term phi div u of
-                           Eq. (5), phi = -T (dp_EOS/dT)_rho, which the
-                           paper's Eq. (6) drops; the LB treatments ignore
-                           it.  0 or 1. */
+  int phi_divu;         /* 1: keep the term phi div u of Eq. (5),
+                           phi = -T (dp_EOS/dT)_rho, which the paper's
+                           Eq. (6) drops: LBM_FD_RK2 adds it to K(T); the LB
+                           treatments add the source w_i phi div u to the
+                           post-collision g_i (u of time t, div u by the
+                           isotropic central difference).  Such lattices
+                           step one step per launch and cannot join a
+                           batch.  0 or 1. */
 } lbm_params;
 
 typedef struct lbm_ctx *lbm_handle;
@@ -262,7 +266,8 @@ typedef struct lbm_batch_ctx *lbm_batch_handle;
 int lbm_batch_workspace_bytes(int count, const lbm_params *p, size_t *bytes);
 
 /* Bind a caller-owned workspace and stream; all p[i].precision must agree
- * and no lattice may be an open channel (wall_x = 2).  Uploads the lattice
+ * and no lattice may be an open channel (wall_x = 2) or keep the phi div u
+ * source (phi_divu = 1).  Uploads the lattice
  * tables (synchronous). */
 int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t bytes,
                      void *hip_stream, lbm_batch_handle *out);

@@ -422,7 +422,9 @@ int lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip
   h->tm = moments_tiling(p->nx, p->ny);
   h->tp = pair_tiling(p->nx, p->ny, (int)env_ll("LBM_PAIR_ROWS", 0), h->st,
                       h->m.sc_on && !h->m.beta_one);
-  h->pair_ok = p->wall_x == 0;
+  // two-step launches: periodic x, and no phi div u source (its velocity
+  // planes are taken per step)
+  h->pair_ok = p->wall_x == 0 && !p->phi_divu;
   h->pair_on = env_ll("LBM_PAIR", fills_chip((long long)h->t.strips * p->ny, h->t.bx) ? 1 : 0) != 0;
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char *)dev_workspace;
@@ -483,6 +485,20 @@ hipError_t one_step(lbm_ctx *h, int treatment) {
                             h->counters, h->stream);
     if (e != hipSuccess) return e;
     return lbmdev::launch_fd(h->m, h->st, h->staging, h->fd, h->buf[1 - h->cur], h->stream);
+  }
+  if (h->p.phi_divu) {
+    // the source phi div u of Eq. (5) needs the velocity of time t at the
+    // neighbours: the moments launch writes it to staging first
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    lbmdev::MomentsOut mo{};
+    mo.rho = h->staging;
+    mo.ux = h->staging + n;
+    mo.uy = h->staging + 2 * n;
+    mo.T = h->staging + 3 * n;
+    hipError_t e = lbmdev::launch_moments(h->m, h->tm, h->st, h->buf[h->cur], mo, h->stream);
+    if (e != hipSuccess) return e;
+    return lbmdev::launch_step_src(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
+                                   h->counters, mo.ux, mo.uy, h->stream);
   }
   return lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], treatment,
                              h->counters, h->stream);

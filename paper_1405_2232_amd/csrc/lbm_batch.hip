@@ -89,6 +89,7 @@ int batch_layout(int count, const lbm_params *p, BatchLayout *B) {
     if (rc) return rc;
     if (p[i].precision != p[0].precision) return LBM_EINVAL;
     if (p[i].wall_x == 2) return LBM_EINVAL;  // open channels step alone
+    if (p[i].phi_divu) return LBM_EINVAL;     // so do lattices with the phi div u source
     Layout L;
     compute_layout(&p[i], &L);
     if (!fits_32bit(L)) return LBM_EINVAL;

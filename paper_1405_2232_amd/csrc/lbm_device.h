@@ -49,7 +49,9 @@ struct Model {
 // MODE_STEP_OPEN is MODE_STEP with the inlet/outlet code of the open
 // channel compiled in (kept out of the other lattices' kernels, where its
 // extra live values would push the row buffers into scratch memory)
-enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_OPEN = 2 };
+// MODE_STEP_SRC is MODE_STEP with the source term phi div u of Eq. (5) in
+// the g update, from velocity planes of time t passed in MomentsOut::ux, uy
+enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_OPEN = 2, MODE_STEP_SRC = 3 };
 
 // Output/side buffers of a moments launch (all optional).
 struct MomentsOut {
@@ -80,6 +82,12 @@ inline int strip_width(int bx) { return bx - 2; }
 // Launchers (stream-ordered, no synchronization).  Return hipError_t.
 hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                        int treatment, unsigned long long *clamp_counter, hipStream_t s);
+// One step with the source term w_i phi div u of Eq. (5) added to the LB g
+// update, phi = -T (dp_EOS/dT)_rho; ux, uy: dense [ny][nx] velocity planes of
+// time t (the moments launch writes them).
+hipError_t launch_step_src(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                           int treatment, unsigned long long *clamp_counter, const double *ux,
+                           const double *uy, hipStream_t s);
 // Two steps in one launch (x periodic; bx 64, 128 or 256 for FP32 storage
 // with the force of Eq. (2), 128 for FP64 or the mixed force of Eq. (4);
 // strips of bx - 6 owned columns): src holds time t, dst receives t + 2.

@@ -61,12 +61,41 @@ struct Prec<ST_F32_LOCAL> {
   using C = double;
 };
 
+// 1/x for x > 0 (not denormal): the hardware reciprocal estimate refined by
+// two Newton-Raphson steps, e = 1 - x r, r <- r + r e, each of which
+// squares the relative error; the result is within an ulp of the correctly
+// rounded quotient, in five instructions instead of the ten of the
+// correctly rounded division sequence (whose chain is also longer).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(s) for s > 0 (not denormal): the hardware reciprocal-square-root
+// estimate y, one Goldschmidt step on g = s y ~ sqrt(s) and h = y/2 ~
+// 1/(2 sqrt(s)) (r = 1/2 - g h; g <- g + g r, h <- h + h r: both errors
+// squared), then a Newton correction of g from the residual s - g^2.
+// Within an ulp of the correctly rounded root, without the range scaling
+// the general square root needs for denormal and huge arguments.
+__device__ __forceinline__ double sqrt_pos(double s) {
+  const double y = __builtin_amdgcn_rsq(s);
+  double g = s * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, s);
+  return fma(d, h, g);
+}
+
 __device__ inline double pressure(const Model &m, double rho, double T) {
   if (m.eos == 1) return rho * m.R * T;
   const double eta = 0.25 * m.b * rho;
   const double num = 1.0 + eta + eta * eta - eta * eta * eta;
   const double om = 1.0 - eta;
-  return rho * m.R * T * num / (om * om * om) - m.a * rho * rho;
+  return rho * m.R * T * num * recip(om * om * om) - m.a * rho * rho;
 }
 
 // psi^2 = 2 (p_EOS - rho c_s^2)/(G c^2); psi clamps to 0 outside the domain.
@@ -81,8 +110,10 @@ __device__ inline void node_psi(const Model &m, double rho, double E, double ir,
   }
   const double T = m.eos_fixed_T ? m.T_eos : E * m.inv_cv * ir;
   s = (pressure(m, rho, T) - rho * (1.0 / 3.0)) * m.two_over_G;
-  if (s >= 0.0) {
-    psi = sqrt(s);
+  if (s > 0.0) {
+    psi = sqrt_pos(s);
+  } else if (s == 0.0) {
+    psi = 0.0;
   } else {
     psi = 0.0;
     clamped = m.count_clamps;
@@ -221,6 +252,29 @@ struct Post {
   }
 };
 
+__device__ inline long long fd_node(const Model &m, int x, int y, bool &ox, bool &oy);
+__device__ inline double dp_dT(const Model &m, double rho);
+
+// div u at node (x, y) by the isotropic central difference
+// sum_i w(|e_i|^2) u(x + e_i) . e_i of dense velocity planes, periodic wrap
+// or, beyond a wall, the boundary node's velocity reversed (no-slip wall
+// halfway out)
+__device__ inline double div_u_at(const Model &m, const double *uxa, const double *uya, int x, int y) {
+  constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  double du = 0.0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+    const int xn = x + ex[i], yn = y + ey[i];
+    bool ox, oy;
+    const long long cn = fd_node(m, xn, yn, ox, oy);
+    const double sgn = ((ox && m.wall_x) || (oy && m.wall_y)) ? -1.0 : 1.0;
+    du += w * (sgn * uxa[cn] * ex[i] + sgn * uya[cn] * ey[i]);
+  }
+  return du;
+}
+
 template <int BX, typename S>
 struct TileLds {
   double psi[4][BX];
@@ -317,7 +371,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     // two more live registers per row cost this kernel more than a division
     double psi, s;
     int cl;
-    node_psi(m, mm.rho, mm.E, 1.0 / mm.rho, psi, s, cl);
+    node_psi(m, mm.rho, mm.E, recip(mm.rho), psi, s, cl);
     L.psi[slot][lane] = psi;
     L.s[slot][lane] = s;
     if (ST == ST_F32_LOCAL) L.rbn[slot][lane] = ref_of(mm.rho);
@@ -391,7 +445,14 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     // collision, Eq. (1) with the forcing term and Eq. (7)/(24), in C, on
     // deviations from the node's own reference
     Post<C> P;
-    P.init(m, mm.rho, mm.E, 1.0 / mm.rho, mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    P.init(m, mm.rho, mm.E, recip(mm.rho), mm.jx, mm.jy, mm.sf, mm.sg, Fx, Fy, treatment);
+    if ((MODE == MODE_STEP_SRC || MODE == MODE_STEP_OPEN) && mo.ux) {
+      // the source of Eq. (5), w_i phi div u with phi = -T (dp_EOS/dT)_rho,
+      // from the velocity planes of time t (lanes owning no column read a
+      // valid node and store nothing)
+      const double Tn = mm.E * m.inv_cv * recip(mm.rho);
+      P.Kg += (C)(-Tn * dp_dT(m, mm.rho) * div_u_at(m, mo.ux, mo.uy, inner ? x : 0, r));
+    }
     const C rs = (C)mm.rho, Es = (C)mm.E;
     const C ux = P.ux, uy = P.uy;
     const C uu = ux * ux + uy * uy;
@@ -435,8 +496,8 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         const int col = kx[i] > 0 ? xr : (kx[i] < 0 ? xl : x);
         const int row = ky[i] > 0 ? rU : (ky[i] < 0 ? rD : r);
         const unsigned cell = inner ? (unsigned)(row * pitch + col) : dummy;
-        bst(db.f, cell * sz + (unsigned)i * pb, 0u, (S)fs);
-        bst(db.g, cell * sz + (unsigned)i * pb, 0u, (S)gs);
+        bst(db.f, cell * sz, (unsigned)i * pb, (S)fs);  // plane offset in the scalar operand
+        bst(db.g, cell * sz, (unsigned)i * pb, (S)gs);
       }
     } else {
 #pragma unroll
@@ -748,7 +809,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     mm.sg = (C)b;
     mm.rho = ref + a;
     mm.E = ref * m.cvT_ref + b;
-    mm.ir = 1.0 / mm.rho;
+    mm.ir = recip(mm.rho);
   };
 
   // force of Eq. (2), or of Eq. (4) with the psi^2 rings (MIX), from the
@@ -917,8 +978,8 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
         C f_out, g_out;
         post_to(P, d, i, rd, f_out, g_out);
         const unsigned cell = own ? (unsigned)(row * pitch + col) : dummy;
-        bst(db.f, cell * sz + (unsigned)i * pb, 0u, (S)f_out);
-        bst(db.g, cell * sz + (unsigned)i * pb, 0u, (S)g_out);
+        bst(db.f, cell * sz, (unsigned)i * pb, (S)f_out);  // plane offset in the scalar operand
+        bst(db.g, cell * sz, (unsigned)i * pb, (S)g_out);
       }
     } else {
 #pragma unroll
@@ -945,8 +1006,8 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
           q = (unsigned)Q9::opp[i];
           cell = self;
         }
-        bst(db.f, cell * sz + q * pb, 0u, (S)f_out);
-        bst(db.g, cell * sz + q * pb, 0u, (S)g_out);
+        bst(db.f, cell * sz, q * pb, (S)f_out);  // q depends on the row only: uniform
+        bst(db.g, cell * sz, q * pb, (S)g_out);
       }
     }
   };
@@ -1200,19 +1261,7 @@ __device__ inline double fd_K(const Model &m, const double *rho, const double *u
   }
   const double div = m.lam_per_rho * rho[c] * lap + gLx * gTx + gLy * gTy;
   double K = -(ux * gTx + uy * gTy) + div / (rho[c] * m.cv);
-  if (m.phi_divu) {
-    double du = 0.0;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const double w = i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-      const int xn = x + ex[i], yn = y + ey[i];
-      bool ox, oy;
-      const long long cn = fd_node(m, xn, yn, ox, oy);
-      const double sgn = ((ox && m.wall_x) || (oy && m.wall_y)) ? -1.0 : 1.0;
-      du += w * (sgn * uxa[cn] * ex[i] + sgn * uya[cn] * ey[i]);
-    }
-    K += -Tc * dp_dT(m, rho[c]) * du / (rho[c] * m.cv);
-  }
+  if (m.phi_divu) K += -Tc * dp_dT(m, rho[c]) * div_u_at(m, uxa, uya, x, y) / (rho[c] * m.cv);
   return K;
 }
 
@@ -1322,6 +1371,17 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
   }
   if (t.pf >= 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
   return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+}
+
+hipError_t launch_step_src(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                           int treatment, unsigned long long *cc, const double *ux, const double *uy,
+                           hipStream_t s) {
+  MomentsOut mo{};
+  mo.ux = const_cast<double *>(ux);
+  mo.uy = const_cast<double *>(uy);
+  if (!ux || !uy) return hipErrorInvalidValue;
+  if (m.wall_x == 2) return launch_tile_st<MODE_STEP_OPEN, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+  return launch_tile_st<MODE_STEP_SRC, 1>(m, t, st, src, dst, treatment, cc, mo, s);
 }
 
 hipError_t launch_pair(const Model &m, const Tiling &t, int st, const void *src, void *dst,

@@ -2,12 +2,13 @@
 against the oracle: the static droplet (EOS at the local T) in FP64 and
 FP32 per-node-reference storage, a ragged walled lattice with gravity and
 both wall conditions, the single-phase ideal-EOS cavity of Sec. III.B, and
-switching treatments mid-run."""
+switching treatments mid-run; the phi div u term of Eq. (5) in the
+finite-difference and the LB treatments."""
 import numpy as np
 import pytest
 
 from gpu_util import compare_fp32dev, compare_fp64, gpu_run, need_gpu, oracle_run, say
-from oracle import CORRECTED, FD_RK2, Oracle
+from oracle import CORRECTED, FD_RK2, PLAIN, Oracle
 from paper_1405_2232_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -86,3 +87,54 @@ def test_phi_divu_fd_parity(walls):
     g = gpu_run(p, rho, T, 800, FD_RK2)
     o = oracle_run(p, rho, T, 800, FD_RK2)
     compare_fp64(g.moments(), o.moments(), what=("fd phi div u", walls))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32local"])
+@pytest.mark.parametrize("treatment", [CORRECTED, PLAIN])
+@pytest.mark.parametrize("walls", [False, True])
+def test_phi_divu_lb_parity(walls, treatment, precision):
+    """The source w_i phi div u of Eq. (5) in the LB g update: GPU against
+    the oracle on a two-phase droplet (EOS at T0 for the plain treatment,
+    which otherwise leaves the EOS domain), periodic, and in a walled box
+    with gravity and both wall conditions (a corner of each kind)."""
+    Tc = inputs.cs_tc()
+    p, rho, T = inputs.static_droplet(nx=70, ny=52, radius=13, seed=9)
+    p["phi_divu"] = True
+    p["eos_fixed_T"] = treatment == PLAIN
+    if walls:
+        p.update(wall_x=True, wall_y=True, thermal_left="adiabatic", thermal_right="dirichlet",
+                 thermal_bottom="dirichlet", thermal_top="dirichlet", T_right=0.87 * Tc,
+                 T_bottom=0.84 * Tc, T_top=0.86 * Tc, gy=-1e-5)
+    say("case lb phi div u", walls, treatment, precision)
+    g = gpu_run(p, rho, T, 800, treatment, precision=precision)
+    assert not g.get_step_pairing()[0]
+    o = oracle_run(p, rho, T, 800, treatment)
+    if precision == "fp64":
+        compare_fp64(g.moments(), o.moments(), what=("lb phi div u", walls, treatment))
+    else:
+        compare_fp32dev(g.moments(), o.moments(), what=("lb phi div u fp32local", walls, treatment))
+
+
+def test_phi_divu_lb_open_channel_parity():
+    """The source in the open channel's kernel variant (inlet and outlet of
+    Sec. III.A), single-phase ideal gas with the beta = 0 force."""
+    mu, Pr = 0.1, 0.71
+    nx, ny = 90, 20
+    p = dict(nx=nx, ny=ny, tau_f=0.5 + 3 * mu, tau_g=0.5 + 3 * mu / Pr, G=1.0, beta=0.0, eos="ideal",
+             R=1.0 / 3.0, cv=1.0, gx=0.0, gy=0.0, wall_x="open", wall_y=True,
+             thermal_left="dirichlet", thermal_right="adiabatic", thermal_bottom="dirichlet",
+             thermal_top="dirichlet", T_left=1.03, T_bottom=0.97, T_top=0.97, u_in=0.05, rho_out=1.0,
+             eos_fixed_T=False, T_eos=1.0, phi_divu=True)
+    one = np.ones((ny, nx))
+    say("case lb phi div u open channel")
+    g = gpu_run(p, one, one, 1500, CORRECTED)
+    o = oracle_run(p, one, one, 1500, CORRECTED)
+    compare_fp64(g.moments(), o.moments(), what=("lb phi div u channel",))
+
+
+def test_phi_divu_lattice_cannot_join_a_batch():
+    from paper_1405_2232_amd.lbm import Batch, LbmError
+    p, rho, T = inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)
+    q = dict(p, phi_divu=True)
+    with pytest.raises(LbmError):
+        Batch([p, q], "fp64")
