@@ -26,7 +26,9 @@ tiling sources are unchanged) with the rate they imply (`measured_GBs`);
 number of steps of the same workload, and again on one core
 (`single_core`, a child process with one OpenMP thread).  Side sections:
 `by_precision` (FP64 and FP32 global-shift storage on the same slab,
-timed like the roofline leg), `batched` (256 uneven lattices stepped
+timed like the roofline leg), `interface_jump` (the slab's temperature
+jump across its interfaces after 20,000 steps of each treatment, the
+forcing-term effect of Eq. (23)), `batched` (256 uneven lattices stepped
 together, autotuned, against the same lattices one at a time in the same
 storage form and in FP64) and
 `steady_state` (wall time of held-out steady-state solves to a 1e-8
@@ -73,6 +75,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-lattice batch section")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state (residual) section")
+    ap.add_argument("--no-jump", action="store_true", help="skip the interface temperature jump section")
+    ap.add_argument("--jump-steps", type=int, default=20000)
     ap.add_argument("--steady-cases", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel 10 times on BYTES (counter calibration)")
@@ -321,6 +325,43 @@ def single_core_baseline(nx, ny, treatment, seconds):
                       % (d["steps"], nx, ny, d["s"])}
 
 
+def interface_jump_section(nx, ny, steps, torch):
+    """The forcing-term effect on the slab (Eq. (23)): the 2048^2 wall
+    slab run `steps` steps with each treatment (FP32 per-node-reference
+    storage; the plain treatment with the EOS at T0, since with the EOS at
+    the local temperature it leaves the EOS domain), then at each of the two
+    interfaces the temperature and density 8 nodes into the vapour and into
+    the liquid from where the density crosses its mid value.  The plain
+    treatment diffuses rho cv T rather than T, so across an interface it
+    drives T_v/T_l towards rho_l/rho_v; the corrected one keeps T
+    continuous (T_v/T_l near 1)."""
+    from paper_1405_2232_amd import inputs
+    from paper_1405_2232_amd.lbm import CORRECTED, PLAIN, Lattice
+    out = {"nx": nx, "ny": ny, "steps": steps, "storage": "fp32local", "probe_depth": 8}
+    for name, treatment, fixed in (("corrected", CORRECTED, False), ("plain_eos_at_T0", PLAIN, True)):
+        p, rho, T = inputs.wall_slab(nx=nx, ny=ny)
+        p["eos_fixed_T"] = fixed
+        g = Lattice(p, "fp32local")
+        g.init_fields(rho, T)
+        g.set_check_interval(1000)
+        g.step(steps, treatment)
+        r, _, _, t = (a[:, 0] for a in g.moments())
+        del g
+        mid = 0.5 * (r[ny // 2] + r[ny // 8])
+        liquid = r > mid
+        cross = [int(k) for k in range(1, ny) if liquid[k] != liquid[k - 1]]
+        sides = []
+        for k in cross:
+            lo, hi = k - 1, k  # the crossing lies between rows lo and hi
+            v, l = (lo - 8, hi + 8) if liquid[hi] else (hi + 8, lo - 8)
+            sides.append({"row": k, "T_v_over_T_l": round(float(t[v] / t[l]), 4),
+                          "rho_l_over_rho_v": round(float(r[l] / r[v]), 4),
+                          "T_v_over_Tc": round(float(t[v] / inputs.cs_tc()), 4),
+                          "T_l_over_Tc": round(float(t[l] / inputs.cs_tc()), 4)})
+        out[name] = sides
+    return out
+
+
 WARM_WEIGHTS = os.path.join(ROOT, "paper_1405_2232_amd", "warmstart_64.npz")
 
 
@@ -515,6 +556,8 @@ def main():
         "by_precision": extra,
         "host_inclusive": host_inclusive,
     }
+    if not args.no_jump:
+        line["interface_jump"] = interface_jump_section(args.nx, args.ny, args.jump_steps, torch)
     if not args.no_batch:
         line["batched"] = batch_section(args.batch_steps, torch)
     if not args.no_steady:

@@ -227,15 +227,16 @@ def residuals(cases, fields, precision="fp64", treatment=CORRECTED, physical=Fal
     return out
 
 
-def screen(cases, preds, precision="fp64", reject=1e-3, factor=3.0, treatment=CORRECTED,
+def screen(cases, preds, precision="fp64", reject=1e-3, factor=1.0, treatment=CORRECTED,
            physical=False):
     """Keep a prediction as the initial state when its one-step residual is
-    at most `reject` or at most `factor` times the cold start's own initial
-    residual (a cold start of these two-phase states already has a one-step
-    residual of about 3e-2, so an absolute 1e-3 alone would reject every
-    start); otherwise, or when non-finite, None (the cold start).  Returns
-    (kept, predicted residuals, cold residuals).  `physical` judges both
-    from the start at rest in the forcing scheme (as in solve)."""
+    at most `reject` or not above `factor` (default 1) times the cold
+    start's own initial residual (a cold start of these two-phase states
+    already has a one-step residual of about 3e-2, so an absolute 1e-3
+    alone would reject every start); otherwise, or when non-finite, None
+    (the cold start).  Returns (kept, predicted residuals, cold residuals).
+    `physical` judges both from the start at rest in the forcing scheme (as
+    in solve)."""
     rp = residuals(cases, preds, precision, treatment, physical)
     rc = residuals(cases, [(c[1], c[2]) for c in cases], precision, treatment, physical)
     keep = [pr if (r <= reject or r <= factor * c) else None for pr, r, c in zip(preds, rp, rc)]
