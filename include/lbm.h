@@ -219,9 +219,12 @@ int lbm_get_state(lbm_handle h, double *state);
 int lbm_set_state(lbm_handle h, const double *state);
 
 /* Checkpoint: write the stored state (raw bytes, any precision), the step
- * count and the clamp count to `path`; lbm_load restores it into a handle
- * created with the same parameters, so that a resumed run is bitwise equal
- * to an uninterrupted one.  LBM_EINVAL on I/O errors or a mismatch. */
+ * count and the clamp count to `path`, with what defines the stored form
+ * (sizes, storage precision and layout, and the deviation shifts rho_ref
+ * and cv T_ref); lbm_load restores it into a handle created with the same
+ * parameters, so that a resumed run is bitwise equal to an uninterrupted
+ * one.  LBM_EINVAL on I/O errors or any mismatch of that form, before
+ * anything is copied to the device. */
 int lbm_save(lbm_handle h, const char *path);
 int lbm_load(lbm_handle h, const char *path);
 

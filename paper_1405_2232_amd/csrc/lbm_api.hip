@@ -45,9 +45,10 @@ int pair_blocks_per_cu(int st, int bx, bool mix) {
   return b < 1 ? 1 : (int)b;
 }
 
-int pair_rows_for(const long long *strips, const int *ny, int count, int st, bool mix) {
+int pair_rows_for(const long long *half_strips, const int *ny, int count, int st, bool mix) {
   // the same round model as pair_tiling, for one band height shared by
-  // many lattices (128-lane blocks)
+  // many lattices (128-lane blocks; half_strips[i] = 64-lane strips per band
+  // row of lattice i)
   const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, 128, mix);
   int maxny = 1;
   for (int i = 0; i < count; ++i) maxny = ny[i] > maxny ? ny[i] : maxny;
@@ -55,7 +56,7 @@ int pair_rows_for(const long long *strips, const int *ny, int count, int st, boo
   int rows = 6;
   for (int r = 6; r <= (maxny > 6 ? maxny : 6); ++r) {
     long long blocks = 0;
-    for (int i = 0; i < count; ++i) blocks += strips[i] * ((ny[i] + r - 1) / r);
+    for (int i = 0; i < count; ++i) blocks += (half_strips[i] * ((ny[i] + r - 1) / r) + 1) / 2;
     const long long cost = ((blocks + slots - 1) / slots) * (2LL * r + 4);
     if (best < 0 || cost < best) {
       best = cost;
@@ -655,13 +656,25 @@ int lbm_set_state(lbm_handle h, const double *state) {
 }
 
 namespace {
+// what defines the stored state: sizes, storage form and layout, and the
+// deviation shifts (rho_ref, cv T_ref) the FP32 forms are taken from
 struct CkptHeader {
   char magic[8];
   int nx, ny, precision, cur;
   long long steps;
   unsigned long long clamps;
   unsigned long long bytes;
+  long long plane;
+  int pitch, rpitch;
+  double rho_ref, cvT_ref;
 };
+
+bool same_state_form(const CkptHeader &hd, const lbm_ctx *h, size_t bytes) {
+  return memcmp(hd.magic, "LBMCKPT2", 8) == 0 && hd.nx == h->p.nx && hd.ny == h->p.ny &&
+         hd.precision == h->p.precision && hd.bytes == bytes && hd.plane == h->L.plane &&
+         hd.pitch == h->L.pitch && hd.rpitch == h->L.rpitch && hd.rho_ref == h->m.rho_ref &&
+         hd.cvT_ref == h->m.cvT_ref;
+}
 }  // namespace
 
 int lbm_save(lbm_handle h, const char *path) {
@@ -672,12 +685,17 @@ int lbm_save(lbm_handle h, const char *path) {
   if (!buf) return LBM_ENOMEM;
   CkptHeader hd;
   memset(&hd, 0, sizeof(hd));
-  memcpy(hd.magic, "LBMCKPT1", 8);
+  memcpy(hd.magic, "LBMCKPT2", 8);
   hd.nx = h->p.nx;
   hd.ny = h->p.ny;
   hd.precision = h->p.precision;
   hd.steps = h->steps;
   hd.bytes = bytes;
+  hd.plane = h->L.plane;
+  hd.pitch = h->L.pitch;
+  hd.rpitch = h->L.rpitch;
+  hd.rho_ref = h->m.rho_ref;
+  hd.cvT_ref = h->m.cvT_ref;
   hipError_t e = hipMemcpyAsync(buf, h->buf[h->cur], bytes, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&hd.clamps, h->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -700,8 +718,7 @@ int lbm_load(lbm_handle h, const char *path) {
   if (!fp) return LBM_EINVAL;
   CkptHeader hd;
   const size_t bytes = h->L.dist_bytes;
-  if (fread(&hd, sizeof(hd), 1, fp) != 1 || memcmp(hd.magic, "LBMCKPT1", 8) != 0 ||
-      hd.nx != h->p.nx || hd.ny != h->p.ny || hd.precision != h->p.precision || hd.bytes != bytes) {
+  if (fread(&hd, sizeof(hd), 1, fp) != 1 || !same_state_form(hd, h, bytes)) {
     fclose(fp);
     return LBM_EINVAL;
   }

@@ -156,16 +156,20 @@ int upload_tiles(lbm_batch_ctx *b) {
   if (!t.empty() && hipMemcpyAsync(b->d_tiles, t.data(), t.size() * sizeof(BatchTile),
                                    hipMemcpyHostToDevice, b->stream) != hipSuccess)
     return LBM_EDEVICE;
-  // two-step tiles: 128 lanes, strips of 122 owned columns
+  // two-step tiles: 128 lanes, strips of 122 owned columns; where a
+  // lattice's last columns fit one wave's strip (at most 58), a block covers
+  // them over two bands, one per wave
   std::vector<BatchTile> pt;
   if (b->pair_ok) {
     for (int i = 0; i < b->count; ++i) {
       if (!b->active[i]) continue;
       const lbm_params &p = b->lat[i]->p;
-      const int strips = (p.nx + 121) / 122;
+      const int full = p.nx / 122, rem = p.nx - 122 * full;
+      const bool halves = rem > 0 && rem <= 58 && !env_ll("LBM_NO_HALVES", 0);
+      const int strips = full + (rem > 0 && !halves ? 1 : 0);
       const int rows = b->prows < p.ny ? b->prows : p.ny;
       const int bands = (p.ny + rows - 1) / rows;
-      for (int band = 0; band < bands; ++band)
+      for (int band = 0; band < bands; ++band) {
         for (int s = 0; s < strips; ++s) {
           BatchTile x;
           memset(&x, 0, sizeof(x));
@@ -176,6 +180,19 @@ int upload_tiles(lbm_batch_ctx *b) {
           x.dir = 1;
           pt.push_back(x);
         }
+        if (halves && (band & 1) == 0) {
+          BatchTile x;
+          memset(&x, 0, sizeof(x));
+          x.lattice = i;
+          x.strip = full;
+          x.band = band;
+          x.band2 = band + 1 < bands ? band + 1 : -1;
+          x.rows = rows;
+          x.dir = 1;
+          x.halves = 1;
+          pt.push_back(x);
+        }
+      }
     }
   }
   if ((int)pt.size() > b->max_tiles) return LBM_EINVAL;
@@ -349,10 +366,13 @@ int lbm_batch_create(int count, const lbm_params *p, void *dev_workspace, size_t
   }
   b->pair_on = env_ll("LBM_PAIR", fills_chip(lanes, b->bx) ? 1 : 0) != 0;
   {
+    // blocks per band row in halves: two per full strip, one for a last
+    // strip of at most 58 columns (two bands share its block), two otherwise
     std::vector<long long> st(count);
     std::vector<int> nys(count);
     for (int i = 0; i < count; ++i) {
-      st[i] = (p[i].nx + 121) / 122;
+      const int full = p[i].nx / 122, rem = p[i].nx - 122 * full;
+      st[i] = 2LL * full + (rem == 0 ? 0 : (rem <= 58 ? 1 : 2));
       nys[i] = p[i].ny;
     }
     const long long er = env_ll("LBM_PAIR_ROWS", 0);

@@ -41,7 +41,7 @@ Tiling moments_tiling(int nx, int ny);
 int one_step_bx(int nx);
 int one_step_rows(long long lanes, int bx, int cap);
 bool fills_chip(long long lanes, int bx);
-int pair_rows_for(const long long *strips, const int *ny, int count, int st, bool mix);
+int pair_rows_for(const long long *half_strips, const int *ny, int count, int st, bool mix);
 Tiling pair_tiling(int nx, int ny, int rows, int st, bool mix);
 int pair_blocks_per_cu(int st, int bx, bool mix);
 int storage_of(const lbm_params *p);

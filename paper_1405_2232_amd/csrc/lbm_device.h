@@ -120,8 +120,11 @@ __host__ __device__ inline size_t ref_plane_offset(const Model &m, int st) {
 // the batch-wide step parity, and its psi-clamp counter; plus the tile list.
 struct BatchTile {
   int lattice, strip, band, rows;
-  int dir;  // +1 up, -1 down
-  int pad[3];
+  int dir;     // +1 up, -1 down
+  int halves;  // two-step tiles: 1 = two 64-lane strips (one per wave) over
+               // the lattice's last columns, bands `band` and `band2`
+  int band2;   // the second wave's band (-1: none)
+  int pad;
 };
 struct BatchTables {
   const Model *models;

@@ -720,12 +720,17 @@ struct PairLds {
   double s2[4][MIX ? BX : 1];
 };
 
-// two steps on strip `strip` (owned columns strip * (BX - 6) ...) and
-// rows y0 .. y0 + n - 1 of one lattice
-// (MIX: the lattice uses the mixed force of Eq. (4), beta != 1)
+// two steps on the strip whose owned columns start at x0 and rows
+// y0 .. y0 + n - 1 of one lattice.  The block's lanes form strips of sw
+// lanes (sw = BX, or 64: each wave its own strip of 58 owned columns, used
+// for the last columns of narrow lattices in a batch); each strip keeps to
+// its own lanes of the LDS rings.  jb = iterations every wave of the block
+// runs (the block's barriers), at least n + 7; a wave past its own n + 7
+// only keeps the barriers.  (MIX: the lattice uses the mixed force of
+// Eq. (4), beta != 1)
 template <int ST, int BX, bool MIX>
 __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *__restrict__ dst_v,
-                          int strip, int y0, int n, int treatment,
+                          int x0, int sw, int y0, int n, int jb, int treatment,
                           unsigned long long *clamp_counter, PairLds<BX, typename Prec<ST>::S, MIX> &L) {
   using S = typename Prec<ST>::S;
   using C = typename Prec<ST>::C;
@@ -734,22 +739,24 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   const unsigned pb = (unsigned)(m.plane * (long long)sizeof(S));
   constexpr unsigned sz = sizeof(S);
 
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x;          // index into the LDS rings
+  const int ll = lane & (sw - 1);          // lane within its strip
+  const int lane0 = lane - ll;             // the strip's first lane
   const int nx = m.nx, ny = m.ny, pitch = m.pitch;
-  const int x0 = strip * (BX - 6);
-  const int nint = min(BX - 6, nx - x0);
-  const bool active = lane < nint + 6;
-  const bool own = lane >= 3 && lane < nint + 3;  // owns its column
-  // a wave with no active lane (the last strip of a lattice) only keeps
-  // the block's barriers
-  const bool wave_live = (lane & ~63) < nint + 6;
+  const int nint = min(sw - 6, nx - x0);
+  const bool active = ll < nint + 6;
+  const bool own = ll >= 3 && ll < nint + 3;  // owns its column
+  // a wave with no active lane (the last strip of a lattice, or no band)
+  // only keeps the block's barriers
+  const bool wave_live = (ll & ~63) < nint + 6 && n > 0;
   auto wrap = [](int v, int len) {
     const int r = v % len;
     return r < 0 ? r + len : r;
   };
-  const int x = active ? wrap(x0 - 3 + lane, nx) : 0;
+  const int x = active ? wrap(x0 - 3 + ll, nx) : 0;
   const int xl = wrap(x - 1, nx), xr = wrap(x + 1, nx);
-  const int c = (lane >= 1 && lane <= BX - 2) ? lane : 1;  // stencil centre in a ring row
+  // stencil centre in a ring row, inside the strip's lanes
+  const int c = (ll >= 1 && ll <= sw - 2) ? lane : lane0 + 1;
 
   auto vrow = [&](int j) { return y0 - 3 + j; };
   auto inside = [&](int v) { return !m.wall_y || (v >= 0 && v < ny); };
@@ -912,7 +919,7 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
     // every lane stores: the lanes that do not collide in this step (the
     // two edges of the block) write inside the ring row, into entries that
     // no owned column reads
-    const int tl = lane > 0 ? lane - 1 : 0, tr = lane < BX - 1 ? lane + 1 : BX - 1;
+    const int tl = ll > 0 ? lane - 1 : lane, tr = ll < sw - 1 ? lane + 1 : lane;
     auto push = [&](int i, C fo, C go) {
       const int exi = Q9::ex[i], eyi = Q9::ey[i];
       S *f = eyi > 0 ? fp : (eyi < 0 ? fm : f0);
@@ -1018,7 +1025,8 @@ __device__ void pair_tile(const Model &m, const void *__restrict__ src_v, void *
   // is 19 moves; loading into R directly would leave half an iteration)
   Row<S> R[2], F[2], P;
   Mom<C> M[2], M2[2];
-  const int J = n + 7;
+  // every stage below is guarded by n, so iterations past n + 7 do nothing
+  const int J = jb;
   if (wave_live) {
     load_row(0, R[0]);
     load_row(1, P);
@@ -1062,7 +1070,8 @@ __global__ __launch_bounds__(BX) void k_pair(Model m, Tiling t, const void *__re
   const int band = tid / t.strips;
   const int y0 = (int)((long long)band * m.ny / t.bands);
   const int y1 = (int)((long long)(band + 1) * m.ny / t.bands);
-  pair_tile<ST, BX, MIX>(m, src, dst, strip, y0, y1 - y0, treatment, clamp_counter, L);
+  pair_tile<ST, BX, MIX>(m, src, dst, strip * (BX - 6), BX, y0, y1 - y0, y1 - y0 + 7, treatment,
+                         clamp_counter, L);
 }
 
 // Two steps of many lattices: one block per tile of the pair tile list
@@ -1082,9 +1091,22 @@ __global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restr
   const int sb = parity ^ bt.phase[t.lattice];
   char *src = base + (sb ? bt.off1[t.lattice] : bt.off0[t.lattice]);
   char *dst = base + (sb ? bt.off0[t.lattice] : bt.off1[t.lattice]);
-  const int y0 = t.band * t.rows;
-  pair_tile<ST, BX, MIX>(m, src, dst, t.strip, y0, min(y0 + t.rows, m.ny) - y0, treatment,
-                    bt.clamp[t.lattice], L);
+  // a full strip of BX lanes over band t.band; or (t.halves) the last
+  // columns of a narrow lattice (at most 58), one wave's strip per band: the
+  // first wave band t.band, the second t.band2 (none when negative), the
+  // block running the longer band's iterations
+  const int na = min(t.band * t.rows + t.rows, m.ny) - t.band * t.rows;
+  int sw = BX, band = t.band, n = na, jb = na + 7;
+  if (t.halves) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nb = t.band2 >= 0 ? min(t.band2 * t.rows + t.rows, m.ny) - t.band2 * t.rows : 0;
+    sw = 64;
+    band = w == 0 ? t.band : max(t.band2, 0);
+    n = w == 0 ? na : nb;
+    jb = max(na, nb) + 7;
+  }
+  pair_tile<ST, BX, MIX>(m, src, dst, t.strip * (BX - 6), sw, band * t.rows, n, jb, treatment,
+                         bt.clamp[t.lattice], L);
 }
 
 // ---------------------------------------------------------------------------

@@ -180,6 +180,34 @@ def test_checkpoint_resume_bitwise(precision, tmp_path):
     assert h.totals()[6] == ta[6] == 250
 
 
+@pytest.mark.parametrize("precision", ["fp32dev", "fp32local"])
+def test_checkpoint_rejects_other_deviation_shifts(precision, tmp_path):
+    """The FP32 forms store deviations from w_i rho_ref and w_i rho cv T_ref:
+    a checkpoint loads only into a handle with the same shifts (LBM_EINVAL
+    otherwise, and the handle's state is left as it was)."""
+    from paper_1405_2232_amd.lbm import EINVAL, Lattice, LbmError
+    p, rho, T = inputs.static_droplet(seed=3)
+    g = Lattice(p, precision, rho_ref=float(rho.mean()), T_ref=float(T.mean()))
+    g.init_fields(rho, T)
+    g.step(20, CORRECTED)
+    path = str(tmp_path / "ck.bin")
+    g.save(path)
+    for rr, tr in ((float(rho.mean()), 1.01 * float(T.mean())), (1.02 * float(rho.mean()), float(T.mean()))):
+        if precision == "fp32local" and rr != float(rho.mean()):
+            continue  # the per-node form has no global density shift
+        h = Lattice(p, precision, rho_ref=rr, T_ref=tr)
+        h.init_fields(rho, T)
+        before = h.get_state()
+        with pytest.raises(LbmError) as e:
+            h.load(path)
+        assert e.value.status == EINVAL
+        assert np.array_equal(h.get_state(), before)
+    same = Lattice(p, precision, rho_ref=float(rho.mean()), T_ref=float(T.mean()))
+    same.init_fields(rho, T)
+    same.load(path)
+    assert np.array_equal(same.get_state(), g.get_state())
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev", "fp32local"])
 def test_state_roundtrip(precision):
     """get_state/set_state is the FP64 view; for FP64 storage it is exact."""
