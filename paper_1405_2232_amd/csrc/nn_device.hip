@@ -1,11 +1,13 @@
 // Convolution-network kernels (gfx950) of the learned warm start: BF16
 // activations and weights, FP32 accumulation on the matrix cores
-// (v_mfma_f32_16x16x16_bf16), FP32 biases, gradients of weights and the
+// (v_mfma_f32_16x16x32_bf16 where the depth is a multiple of 32, else
+// v_mfma_f32_16x16x16_bf16), FP32 biases, gradients of weights and the
 // optimizer state.
 //
-// Matrix-core operand layout (one 64-lane wave, 16x16x16 product):
-//   A (16 x 16, rows i, depth k): lane l holds A[l % 16][4 (l / 16) + 0..3];
-//   B (16 x 16, depth k, cols j): lane l holds B[4 (l / 16) + 0..3][l % 16];
+// Matrix-core operand layout (one 64-lane wave, 16x16xKD product, KD = 16
+// or 32, G = KD / 4 depth values per lane):
+//   A (16 x KD, rows i, depth k): lane l holds A[l % 16][G (l / 16) + 0..G-1];
+//   B (KD x 16, depth k, cols j): lane l holds B[G (l / 16) + 0..G-1][l % 16];
 //   D (16 x 16):                  lane l holds D[4 (l / 16) + 0..3][l % 16].
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,7 +17,15 @@
 namespace lbmnn {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// one matrix-core product of depth 32: A, B eight BF16 values per lane
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a),
+                                                 __builtin_bit_cast(bf16v8, b), c, 0, 0, 0);
+}
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -31,12 +41,15 @@ __device__ inline int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - 
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution as an implicit product: rows = 16 pixels of one image row
-// per wave (64 per block), depth = (tap, input channel) in chunks of 16,
-// columns = output channels in NB blocks of 16.  The A operand is read
-// straight from the NHWC input (four consecutive channels = 8 bytes per
-// lane); the B operand from the [cout][9][cin] weights (cached).
-template <int NB>
+// per wave (64 per block), depth = (tap, input channel) in chunks of KD (32
+// when the input channels are a multiple of 32, else 16), columns = output
+// channels in NB blocks of 16.  The A operand is read straight from the
+// NHWC input (KD/4 consecutive channels per lane); the B operand from the
+// [cout][9][cin] weights (cached).
+template <int NB, int KD>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+  typedef short vec __attribute__((ext_vector_type(KD / 4)));
+  constexpr int G = KD / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int segs = (a.W + 63) >> 6;
   int bid = blockIdx.x;
@@ -46,7 +59,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int b = bid / a.H;
   const int x0 = seg * 64 + wave * 16;
   const int px = x0 + (lane & 15);
-  const int k4 = (lane >> 4) * 4;
+  const int kg = (lane >> 4) * G;
   f32x4 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -60,24 +73,27 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       else
         ok = ok && sx >= 0 && sx < a.W;
       const size_t pix = ((size_t)b * a.H + (ok ? sy : 0)) * a.W + (ok ? sx : 0);
-      const uint16_t *xp = a.x + pix * a.xcs + a.xco + k4;
-      const uint16_t *mp = a.mask ? a.mask + pix * a.mcs + a.mco + k4 : nullptr;
-      const uint16_t *wp = a.w + ((size_t)(lane & 15) * 9 + tap) * a.cin + k4;
-      for (int c0 = 0; c0 < a.cin; c0 += 16) {
-        bf16x4 av = bf16x4{0, 0, 0, 0};
+      const uint16_t *xp = a.x + pix * a.xcs + a.xco + kg;
+      const uint16_t *mp = a.mask ? a.mask + pix * a.mcs + a.mco + kg : nullptr;
+      const uint16_t *wp = a.w + ((size_t)(lane & 15) * 9 + tap) * a.cin + kg;
+      for (int c0 = 0; c0 < a.cin; c0 += KD) {
+        vec av = (vec)0;
         if (ok) {
-          av = *(const bf16x4 *)(xp + c0);
+          av = *(const vec *)(xp + c0);
           if (mp) {
-            const bf16x4 mv = *(const bf16x4 *)(mp + c0);
+            const vec mv = *(const vec *)(mp + c0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < G; ++j)
               if (!(bf2f((uint16_t)mv[j]) > 0.f)) av[j] = 0;
           }
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          const bf16x4 bv = *(const bf16x4 *)(wp + (size_t)nb * 16 * 9 * a.cin + c0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
+          const vec bv = *(const vec *)(wp + (size_t)nb * 16 * 9 * a.cin + c0);
+          if constexpr (KD == 32)
+            acc[nb] = mfma32(av, bv, acc[nb]);
+          else
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
         }
       }
     }
@@ -111,11 +127,11 @@ __global__ void k_flip(const uint16_t *w, uint16_t *wt, int cin, int cout) {
 // Weight gradient: for one tap per block (blockIdx.y) and one chunk of image
 // rows (blockIdx.x), D[co][ci] = sum_p dy'(p, co) x(p + off, ci), depth =
 // pixels.  Each 64-pixel segment of dy' and of the shifted x is staged in
-// LDS transposed to [channel][pixel] (rows padded to 68 halves), so that a
-// lane's four consecutive pixels are one 8-byte LDS read.  The block's
-// partial D goes to its own slot of `part`; k_wgrad_reduce sums the slots
-// in order.
-constexpr int kLdsPitch = 68;
+// LDS transposed to [channel][pixel] (rows padded to 72 halves, 16-byte
+// aligned), so that a lane's eight consecutive pixels are one 16-byte LDS
+// read; two depth-32 products per segment.  The block's partial D goes to
+// its own slot of `part`; k_wgrad_reduce sums the slots in order.
+constexpr int kLdsPitch = 72;
 constexpr int kMaxTilesPerWave = 8;
 
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
@@ -181,16 +197,16 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         bacc += s;
       }
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int q4 = ks * 16 + (lane >> 4) * 4;
+      for (int ks = 0; ks < 2; ++ks) {
+        const int q8 = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
         for (int i = 0; i < kMaxTilesPerWave; ++i) {
           const int tile = wave + 4 * i;
           if (tile < ntiles) {
             const int ib = tile / nbk, jb = tile % nbk;
-            const bf16x4 av = *(const bf16x4 *)(lds_dy + (ib * 16 + (lane & 15)) * kLdsPitch + q4);
-            const bf16x4 bv = *(const bf16x4 *)(lds_x + (jb * 16 + (lane & 15)) * kLdsPitch + q4);
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i], 0, 0, 0);
+            const bf16x8 av = *(const bf16x8 *)(lds_dy + (ib * 16 + (lane & 15)) * kLdsPitch + q8);
+            const bf16x8 bv = *(const bf16x8 *)(lds_x + (jb * 16 + (lane & 15)) * kLdsPitch + q8);
+            acc[i] = mfma32(av, bv, acc[i]);
           }
         }
       }
@@ -478,20 +494,30 @@ static int grid_for(size_t n, int threads = 256) {
   return g < 1 ? 1 : (int)g;
 }
 
-hipError_t launch_conv(const ConvArgs &a, hipStream_t s) {
-  const int blocks = a.B * a.H * ((a.W + 63) / 64);
+template <int KD>
+static hipError_t launch_conv_kd(const ConvArgs &a, int blocks, hipStream_t s) {
   switch ((a.cout + 15) / 16) {
-    case 1: hipLaunchKernelGGL(k_conv<1>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_conv<2>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_conv<3>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_conv<4>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL(k_conv<5>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_conv<6>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL(k_conv<7>, dim3(blocks), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_conv<8>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_conv<1, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_conv<2, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_conv<3, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_conv<4, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_conv<5, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_conv<6, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_conv<7, KD>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_conv<8, KD>), dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_conv(const ConvArgs &a, hipStream_t s) {
+  const int blocks = a.B * a.H * ((a.W + 63) / 64);
+  // depth-32 products where the input channels allow them (every layer but
+  // the first, whose 16 input planes are the padded fields) and their
+  // 16-byte loads are aligned (channel strides and offsets multiples of 8)
+  const bool kd32 = a.cin % 32 == 0 && a.xcs % 8 == 0 && a.xco % 8 == 0 &&
+                    (!a.mask || (a.mcs % 8 == 0 && a.mco % 8 == 0));
+  return kd32 ? launch_conv_kd<32>(a, blocks, s) : launch_conv_kd<16>(a, blocks, s);
 }
 
 hipError_t launch_flip(const uint16_t *w, uint16_t *wt, int cin, int cout, hipStream_t s) {

@@ -76,6 +76,7 @@ SHAPES = [  # B, H, W, cin, cout, wrap, (xcs, xco), (ycs, yco)
     (2, 5, 70, 32, 48, 1, (40, 8), (52, 4)),
     (1, 9, 33, 16, 16, 0, (16, 0), (20, 4)),
     (3, 4, 64, 64, 128, 1, (64, 0), (128, 0)),
+    (1, 6, 40, 32, 32, 0, (36, 4), (32, 0)),  # depth 32 but unaligned: the depth-16 path
 ]
 
 
