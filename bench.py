@@ -409,12 +409,15 @@ def steady_section(count, torch, n=64, target=1e-8, cap=600000):
         inits, _, _ = warmstart.screen(cases, preds, physical=True)
         t_inf = time.perf_counter() - t0
         warmp = warmstart.solve(cases, inits=inits, target=target, cap=cap, keep=False, physical=True)
-        both = [i for i in range(count) if cold["steps"][i] is not None and warmp["steps"][i] is not None]
+        rawp = warmstart.solve(cases, inits=preds, target=target, cap=cap, keep=False, physical=True)
+        capped = lambda st: sum(cap if s is None else s for s in st)  # noqa: E731
         ps.update({"warm_s": round(warmp["wall_s"] + t_inf, 2),
                    "warm_converged": sum(s is not None for s in warmp["steps"]),
                    "warm_accepted": sum(p is not None for p in inits),
-                   "steps_cold_vs_warm_on_both": [sum(cold["steps"][i] for i in both),
-                                                  sum(warmp["steps"][i] for i in both)],
+                   "steps_capped_cold_vs_warm": [capped(coldp["steps"]), capped(warmp["steps"])],
+                   "every_prediction_s": round(rawp["wall_s"] + t_inf, 2),
+                   "every_prediction_converged": sum(s is not None for s in rawp["steps"]),
+                   "steps_capped_every_prediction": capped(rawp["steps"]),
                    "speedup_warm_vs_plain": round(plain["wall_s"] / (warmp["wall_s"] + t_inf), 2)})
     out["physical_start"] = ps
     return out

@@ -74,7 +74,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     for k in range(0, len(train_cases), args.batch_solve):
         part = train_cases[k:k + args.batch_solve]
-        r = solve(part, target=args.train_target, cap=args.train_cap, physical=args.physical)
+        r = solve(part, target=args.train_target, cap=args.train_cap, physical=args.physical, log=log)
         for i, st in enumerate(r["steps"]):
             if st is not None:
                 keep.append(k + i)
@@ -111,13 +111,14 @@ def _evaluate(args, ws, test_cases, res, t_all):
     import time
     from paper_1405_2232_amd.warmstart import screen, solve
     ph = args.physical
-    cold = solve(test_cases, target=args.target, cap=args.cap, keep=False, physical=ph)
+    cold = solve(test_cases, target=args.target, cap=args.cap, keep=False, physical=ph, log=log)
     t0 = time.perf_counter()
     preds = ws.predict(test_cases)
     inits, rp, rc = screen(test_cases, preds, factor=args.factor, physical=ph)
     infer_s = time.perf_counter() - t0
-    warm = solve(test_cases, inits=inits, target=args.target, cap=args.cap, keep=False, physical=ph)
-    raw = solve(test_cases, inits=preds, target=args.target, cap=args.cap, keep=False, physical=ph)
+    log("screened: %d of %d predictions kept" % (sum(p is not None for p in inits), len(inits)))
+    warm = solve(test_cases, inits=inits, target=args.target, cap=args.cap, keep=False, physical=ph, log=log)
+    raw = solve(test_cases, inits=preds, target=args.target, cap=args.cap, keep=False, physical=ph, log=log)
     both = [i for i in range(len(test_cases)) if cold["steps"][i] is not None and warm["steps"][i] is not None]
     cs = np.array([cold["steps"][i] for i in both], dtype=float)
     wsteps = np.array([warm["steps"][i] for i in both], dtype=float)

@@ -27,7 +27,7 @@ def _scalars(cases, Tc):
 
 
 def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=1000,
-          treatment=CORRECTED, graph=50, keep=True, physical=False):
+          treatment=CORRECTED, graph=50, keep=True, physical=False, log=None, log_every=20000):
     """Run every case (a list of (params, rho, T)) from its initial fields
     (or from inits[i] = (rho, T) when given) to the residual target, in one
     batch with converged lattices frozen.  `physical` starts each lattice
@@ -37,7 +37,8 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
     residual stalls between 1e-7 and 1e-6 (rounding of the stored
     distributions).  Returns a dict with per-case steps (None when the cap or
     a non-finite value stopped it), the wall time, and (keep) the final
-    fields as FP64 host arrays."""
+    fields as FP64 host arrays.  `log` (a callable) gets a progress line
+    every `log_every` steps."""
     import torch
     t0 = time.perf_counter()
     refs = [(float(r.mean()), float(t.mean())) for _, r, t in cases]
@@ -67,6 +68,9 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
                     failed[i] = True
                 elif res[i] < target:
                     steps[i] = done
+        if log and done % log_every == 0:
+            log("solve: %d steps, %d of %d open, %.1f s" % (
+                done, sum(steps[i] is None and not failed[i] for i in range(n)), n, time.perf_counter() - t0))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = {"steps": steps, "failed": failed, "wall_s": wall, "cap": cap}

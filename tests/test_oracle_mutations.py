@@ -117,8 +117,8 @@ MUTATIONS = [
      "double num = 1.0 + eta + eta * eta + eta * eta * eta;\n  double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);\n  return rho * p->R * T",
      [pins.test_cs_eos_critical_point]),
     ("velocity without the half force",
-     "      double ux = (h->jx[c] + 0.5 * Fx[c]) / r;\n      double uy = (h->jy[c] + 0.5 * Fy[c]) / r;\n      h->ux[c] = ux;",
-     "      double ux = h->jx[c] / r;\n      double uy = h->jy[c] / r;\n      h->ux[c] = ux;",
+     "      double ux = (h->jx[c] + 0.5 * Fx[c]) / r;\n      double uy = (h->jy[c] + 0.5 * Fy[c]) / r;\n      if (!src) {",
+     "      double ux = h->jx[c] / r;\n      double uy = h->jy[c] / r;\n      if (!src) {",
      [pins.test_momentum_budget_with_gravity, lambda: pins.test_slab_steady_state_forcing_term_effect(1.0)]),
     ("temperature moment without c_v",
      "h->T[c] = e / (r * p->cv);", "h->T[c] = e / r;",
