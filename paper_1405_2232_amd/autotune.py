@@ -13,8 +13,8 @@ import json
 import os
 
 CANDIDATES = ((64, 4), (64, 8), (128, 4), (128, 8), (128, 16), (256, 4), (256, 8), (256, 16))
-# band heights of the two-step kernel
-PAIR_ROWS = (12, 16, 24, 32, 48)
+# band heights of the two-step kernel (the library's own pick is timed too)
+PAIR_ROWS = (16, 24, 32, 40, 48, 64)
 # single lattices also take 512-lane blocks (batches do not)
 SINGLE_CANDIDATES = CANDIDATES + ((512, 4), (512, 8))
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
@@ -96,10 +96,11 @@ def tune_pair_rows(make, kind, precision, sizes, treatment=1, steps=20, candidat
     if key in cache:
         return int(cache[key]["best"]), cache[key].get("ms", {})
     obj = make()
-    if not obj.get_step_pairing()[0]:
+    active, own = obj.get_step_pairing()
+    if not active:
         return 0, {}
     times = {}
-    for rows in candidates:
+    for rows in sorted(set(candidates) | {own}):
         obj.set_step_pairing(True, rows)
         times[str(rows)] = _time(obj, steps + (steps & 1), treatment)
     del obj

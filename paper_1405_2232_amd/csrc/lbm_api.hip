@@ -5,7 +5,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <functional>
 #include <new>
+#include <vector>
 
 #include "lbm_ctx.h"
 
@@ -26,12 +29,6 @@ static int device_cus() {
 
 int one_step_bx(int nx) { return nx >= 192 ? 256 : (nx > 62 ? 128 : 64); }
 
-// Band height of the one-step kernel for `lanes` strip-rows (strips x rows,
-// summed over a batch's lattices) of blocks of bx lanes: `cap` rows when the
-// work fills the chip many times over, fewer (down to 2) when the blocks
-// would not fill the 2-waves-per-SIMD slots, because a block walks its band
-// row after row and small lattices are bound by that latency (eight 64^2
-// lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
 // two-step blocks of bx lanes that fit on one CU: at most two waves per
 // SIMD for FP32 storage and one for FP64 (registers), and no more than the
 // 160 KB of LDS hold (the rings: 3 x 18 distributions, 2 x 4 psi rows, 2 x
@@ -45,21 +42,60 @@ int pair_blocks_per_cu(int st, int bx, bool mix) {
   return b < 1 ? 1 : (int)b;
 }
 
+// Band height shared by the lattices of a batch for the two-step kernel.
+// half_strips[i] = 64-lane strips per band row of lattice i: two per full
+// strip of 122 columns, plus one for a last strip of at most 58 columns
+// (whose block covers two bands, one per wave) or two for a wider one.  For
+// each candidate height the launch is simulated as the batch builds it:
+// tiles grouped by lattice, cost = the taller band's rows + 7 pipeline rows,
+// cut into eight runs of equal cost (one per XCD), each run longest first,
+// each XCD filling its slots in list order; the height with the shortest
+// simulated launch wins (the taller one on ties: fewer halo rows).
 int pair_rows_for(const long long *half_strips, const int *ny, int count, int st, bool mix) {
-  // the same round model as pair_tiling, for one band height shared by
-  // many lattices (128-lane blocks; half_strips[i] = 64-lane strips per band
-  // row of lattice i)
   const long long slots = (long long)device_cus() * pair_blocks_per_cu(st, 128, mix);
-  int maxny = 1;
+  const int per_xcd = slots >= 8 ? (int)(slots / 8) : 1;
+  int maxny = 6;
   for (int i = 0; i < count; ++i) maxny = ny[i] > maxny ? ny[i] : maxny;
+  const int top = maxny < 160 ? maxny : 160;
+  std::vector<int> cost;
+  std::vector<long long> heap;
   long long best = -1;
   int rows = 6;
-  for (int r = 6; r <= (maxny > 6 ? maxny : 6); ++r) {
-    long long blocks = 0;
-    for (int i = 0; i < count; ++i) blocks += (half_strips[i] * ((ny[i] + r - 1) / r) + 1) / 2;
-    const long long cost = ((blocks + slots - 1) / slots) * (2LL * r + 4);
-    if (best < 0 || cost < best) {
-      best = cost;
+  for (int r = 6; r <= top; ++r) {
+    cost.clear();
+    long long total = 0;
+    for (int i = 0; i < count; ++i) {
+      const int rr = r < ny[i] ? r : ny[i];
+      const int bands = (ny[i] + rr - 1) / rr;
+      const long long full = half_strips[i] / 2;
+      const bool half = (half_strips[i] & 1) != 0;
+      for (int b = 0; b < bands; ++b) {
+        const int n = (b + 1) * rr < ny[i] ? rr : ny[i] - b * rr;
+        for (long long s = 0; s < full; ++s) cost.push_back(n + 7);
+        if (half && (b & 1) == 0) {
+          const int nb = b + 1 < bands ? ((b + 2) * rr < ny[i] ? rr : ny[i] - (b + 1) * rr) : 0;
+          cost.push_back((n > nb ? n : nb) + 7);
+        }
+      }
+    }
+    for (int c : cost) total += c;
+    long long make = 0, acc = 0;
+    size_t k = 0;
+    for (int x = 0; x < 8 && k < cost.size(); ++x) {
+      const size_t first = k;
+      while (k < cost.size() && (x == 7 || acc * 8 < total * (x + 1))) acc += cost[k++];
+      std::vector<int> run(cost.begin() + first, cost.begin() + k);
+      std::sort(run.begin(), run.end(), [](int a, int b) { return a > b; });
+      heap.assign(per_xcd, 0);  // min-heap of slot finishing times
+      for (int c : run) {
+        std::pop_heap(heap.begin(), heap.end(), std::greater<long long>());
+        heap.back() += c;
+        std::push_heap(heap.begin(), heap.end(), std::greater<long long>());
+      }
+      make = std::max(make, *std::max_element(heap.begin(), heap.end()));
+    }
+    if (best < 0 || make <= best) {
+      best = make;
       rows = r;
     }
   }
@@ -77,6 +113,12 @@ bool fills_chip(long long lanes, int bx) {
   return lanes >= 6 * slots;
 }
 
+// Band height of the one-step kernel for `lanes` strip-rows (strips x rows,
+// summed over a batch's lattices) of blocks of bx lanes: `cap` rows when the
+// work fills the chip many times over, fewer (down to 2) when the blocks
+// would not fill the 2-waves-per-SIMD slots, because a block walks its band
+// row after row and small lattices are bound by that latency (eight 64^2
+// lattices: 14.3 us per step at 8 rows, 7.0 us at 2).
 int one_step_rows(long long lanes, int bx, int cap) {
   const long long slots = (long long)device_cus() * (512 / bx);
   long long r = (lanes + slots - 1) / slots;

@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -128,6 +129,50 @@ void drop_graphs(lbm_batch_ctx *b) {
   }
 }
 
+// Row iterations a two-step tile runs (its block's duration in a full
+// chip): the taller band's rows plus the seven of the pipeline.
+int pair_cost(const BatchTile &x, const std::vector<lbm_ctx *> &lat) {
+  const int ny = lat[x.lattice]->p.ny;
+  const auto rows_of = [&](int band) { return band < 0 ? 0 : std::min(band * x.rows + x.rows, ny) - band * x.rows; };
+  const int n = x.halves ? std::max(rows_of(x.band), rows_of(x.band2)) : rows_of(x.band);
+  return n + 7;
+}
+
+// Orders two-step tiles for the launch's XCD mapping (block b runs list
+// entry (b mod 8) * per + b / 8 on XCD b mod 8, so each XCD takes one
+// contiguous run of the list in order).  The list, grouped by lattice, is
+// cut into eight runs of equal row iterations; each run is sorted longest
+// first (stably, so equal tiles of one lattice stay neighbours and share
+// their halo rows in L2), which leaves the short ragged bands to fill the
+// last slots; runs are padded to one length with empty tiles.
+void order_for_xcds(std::vector<BatchTile> &pt, const std::vector<lbm_ctx *> &lat) {
+  long long total = 0;
+  for (const BatchTile &x : pt) total += pair_cost(x, lat);
+  std::vector<std::vector<BatchTile>> run(8);
+  long long acc = 0;
+  int r = 0;
+  for (const BatchTile &x : pt) {
+    while (r < 7 && acc * 8 >= total * (r + 1)) ++r;
+    run[r].push_back(x);
+    acc += pair_cost(x, lat);
+  }
+  size_t per = 0;
+  for (auto &v : run) {
+    std::stable_sort(v.begin(), v.end(), [&](const BatchTile &a, const BatchTile &b) {
+      return pair_cost(a, lat) > pair_cost(b, lat);
+    });
+    per = std::max(per, v.size());
+  }
+  BatchTile none;
+  memset(&none, 0, sizeof(none));
+  none.lattice = -1;
+  pt.clear();
+  for (auto &v : run) {
+    v.resize(per, none);
+    pt.insert(pt.end(), v.begin(), v.end());
+  }
+}
+
 // tile list of the active lattices; consecutive tiles are neighbouring bands
 // of one lattice (the kernel deals them to XCDs in runs); odd bands walk down
 int upload_tiles(lbm_batch_ctx *b) {
@@ -194,6 +239,11 @@ int upload_tiles(lbm_batch_ctx *b) {
         }
       }
     }
+  }
+  if (!pt.empty() && env_ll("LBM_BATCH_ORDER", 1) != 0) {
+    std::vector<BatchTile> ordered = pt;
+    order_for_xcds(ordered, b->lat);
+    if ((int)ordered.size() <= b->max_tiles) pt.swap(ordered);  // padding fits the table
   }
   if ((int)pt.size() > b->max_tiles) return LBM_EINVAL;
   b->nptiles = (int)pt.size();

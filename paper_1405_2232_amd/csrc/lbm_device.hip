@@ -1087,6 +1087,7 @@ __global__ __launch_bounds__(BX) void k_pair_batch(BatchTables bt, char *__restr
   }
   if (tid >= bt.ntiles) return;
   const BatchTile t = bt.tiles[tid];
+  if (t.lattice < 0) return;  // padding of an XCD's run
   const Model m = bt.models[t.lattice];
   const int sb = parity ^ bt.phase[t.lattice];
   char *src = base + (sb ? bt.off1[t.lattice] : bt.off0[t.lattice]);
