@@ -201,14 +201,19 @@ Tiling pair_tiling(int nx, int ny, int rows, int st, bool mix) {
   return t;
 }
 
-// Tiling of the moments and reduction launches: fixed (8-row bands), so
-// that the per-block partials buffer it sizes does not depend on the
-// device or the environment.
+// Tiling of the moments and reduction launches: a function of the lattice
+// size alone, so that the per-block partials buffer it sizes does not
+// depend on the device or the environment.  8-row bands where that still
+// gives 1024 blocks; shorter bands (down to one row) on smaller lattices,
+// whose moments pass is bound by one block's row walk (a 64^2 lattice:
+// 8 blocks of 8 rows take about 20 us).
 Tiling moments_tiling(int nx, int ny) {
   Tiling t;
   t.bx = one_step_bx(nx);
   t.strips = (nx + t.bx - 3) / (t.bx - 2);
-  t.rows = ny < 8 ? ny : 8;
+  const long long want = (long long)t.strips * ny / 1024;  // rows per band for 1024 blocks
+  t.rows = want >= 8 ? 8 : (want < 1 ? 1 : (int)want);
+  if (t.rows > ny) t.rows = ny;
   t.bands = (ny + t.rows - 1) / t.rows;
   t.xcd = 1;
   t.alt = 1;

@@ -524,15 +524,24 @@ int lbm_batch_step_residuals(lbm_batch_handle b, int treatment, double *residual
     rc = run_moments(b->lat[i], nullptr, nullptr, nullptr, nullptr, 0, 1);
     if (rc) return rc;
   }
+  // every lattice's totals and clamp counter come back before one wait
+  std::vector<double> reds((size_t)b->count * lbmdev::kPartials, 0.0);
+  std::vector<unsigned long long> clamp(b->count, 0);
+  for (int i = 0; i < b->count; ++i) {
+    if (!b->active[i]) continue;
+    if (hipMemcpyAsync(&reds[(size_t)i * lbmdev::kPartials], b->lat[i]->out,
+                       lbmdev::kPartials * sizeof(double), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipMemcpyAsync(&clamp[i], b->lat[i]->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       b->stream) != hipSuccess)
+      return LBM_EDEVICE;
+  }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
   for (int i = 0; i < b->count; ++i) {
     residuals[i] = -1.0;
     status[i] = LBM_OK;
     if (!b->active[i]) continue;
-    double red[lbmdev::kPartials];
-    unsigned long long clamps = 0;
-    rc = fetch_totals(b->lat[i], red, &clamps);
-    if (rc) return rc;
+    const double *red = &reds[(size_t)i * lbmdev::kPartials];
+    const unsigned long long clamps = clamp[i];
     const double r1 = red[6] > 0.0 ? red[5] / red[6] : 0.0;
     const double r2 = red[8] > 0.0 ? red[7] / red[8] : 0.0;
     residuals[i] = r1 > r2 ? r1 : r2;

@@ -1188,25 +1188,39 @@ __global__ void k_ref_from_rho(Model m, void *__restrict__ dst_v, const double *
   ref[(long long)y * m.rpitch + x] = (_Float16)ref_of(rho[c]);
 }
 
+// Reduces the per-block partials (sums for entries 0-4, maxima for the
+// rest) in one pass: each lane folds a strided set of blocks, the waves
+// fold their lanes by butterfly shuffles, and the first lanes fold the four
+// waves in a fixed order (the result is reproducible run to run).
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks,
                                                   double *__restrict__ out) {
-  __shared__ double red[256];
-  const int tx = threadIdx.x;
-  for (int k = 0; k < kPartials; ++k) {
-    const bool is_max = k >= 5;
-    double a = 0.0;
-    for (int b = tx; b < nblocks; b += 256) {
-      const double v = partials[(long long)b * kPartials + k];
-      a = is_max ? fmax(a, v) : a + v;
+  __shared__ double red[kPartials][4];
+  const int tx = threadIdx.x, lane = tx & 63, w = tx >> 6;
+  double a[kPartials];
+#pragma unroll
+  for (int k = 0; k < kPartials; ++k) a[k] = 0.0;
+  for (int b = tx; b < nblocks; b += 256) {
+    const double *p = partials + (long long)b * kPartials;
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) a[k] = k >= 5 ? fmax(a[k], p[k]) : a[k] + p[k];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) {
+      const double v = __shfl_xor(a[k], o, 64);
+      a[k] = k >= 5 ? fmax(a[k], v) : a[k] + v;
     }
-    red[tx] = a;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tx < w) red[tx] = is_max ? fmax(red[tx], red[tx + w]) : red[tx] + red[tx + w];
-      __syncthreads();
-    }
-    if (tx == 0) out[k] = red[0];
-    __syncthreads();
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) red[k][w] = a[k];
+  }
+  __syncthreads();
+  if (tx < kPartials) {
+    const int k = tx;
+    out[k] = k >= 5 ? fmax(fmax(red[k][0], red[k][1]), fmax(red[k][2], red[k][3]))
+                    : (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
   }
 }
 

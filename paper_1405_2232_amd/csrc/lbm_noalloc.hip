@@ -10,7 +10,8 @@
 namespace {
 
 // Largest moments launch served: 32768 blocks (a lattice of up to about
-// 5,800^2 nodes; the moments tiling has 254-column strips and 8-row bands).
+// 5,800^2 nodes; at that size the moments tiling has 254-column strips and
+// 8-row bands).
 constexpr int kMaxBlocks = 32768;
 constexpr size_t kPartialDoubles = (size_t)kMaxBlocks * lbmdev::kPartials;
 // partials, then the reduced totals (kPartials doubles, 256-byte aligned)
