@@ -290,11 +290,23 @@ def cpu_baseline(p, rho, T, treatment, seconds):
     cells = p["nx"] * p["ny"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
-           "kind": "oracle",
+           "kind": "oracle", "cpu_model": host_cpu_model(),
            "sample": "%d steps of the %dx%d slab (FP64 oracle, %d OpenMP threads, %.1f s)"
                      % (n, p["nx"], p["ny"], cores, el)}
     out["single_core"] = single_core_baseline(p["nx"], p["ny"], treatment, seconds / 2)
     return out
+
+
+def host_cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def single_core_baseline(nx, ny, treatment, seconds):
