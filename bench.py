@@ -26,7 +26,8 @@ tiling sources are unchanged) with the rate they imply (`measured_GBs`);
 number of steps of the same workload, and again on one core
 (`single_core`, a child process with one OpenMP thread).  Side sections:
 `by_precision` (FP64 and FP32 global-shift storage on the same slab,
-timed like the roofline leg), `interface_jump` (the slab's temperature
+timed like the roofline leg), `by_treatment` (the slab with each of the
+three temperature treatments), `interface_jump` (the slab's temperature
 jump across its interfaces after 20,000 steps of each treatment, the
 forcing-term effect of Eq. (23)), `batched` (256 uneven lattices stepped
 together, autotuned, against the same lattices one at a time in the same
@@ -270,6 +271,33 @@ def kernel_timing(g, treatment, torch, warm=100, runs=5, launches=200):
     times = sorted(timed_steps(g, launches * per, treatment, torch) * per for _ in range(runs))
     return {"median": times[runs // 2], "min": times[0], "max": times[-1],
             "steps_per_launch": per, "runs": runs, "launches": launches, "warmup": warm}
+
+
+def treatment_section(p, rho, T, args, torch, warm=100, runs=5, steps=200):
+    """The slab in the benchmark's storage form with each temperature
+    treatment: ms per step (median of `runs` event-timed runs of `steps`
+    steps after `warm` untimed ones, no periodic check) and MLUPS.  The
+    plain treatment holds the EOS at T0 (with the EOS at the local
+    temperature it leaves the EOS domain); the finite-difference treatment
+    runs the one-step kernel for f and two stencil passes for T per step."""
+    from paper_1405_2232_amd.lbm import CORRECTED, FD_RK2, PLAIN, Lattice
+    cells = p["nx"] * p["ny"]
+    out = {}
+    for name, treatment, fixed in (("plain_eq7_eos_at_T0", PLAIN, True), ("corrected_eq24", CORRECTED, False),
+                                   ("finite_difference_eq26", FD_RK2, False)):
+        q = dict(p, eos_fixed_T=fixed)
+        g = Lattice(q, args.precision)
+        g.init_fields(rho, T)
+        if args.no_pair:
+            g.set_step_pairing(False)
+        g.set_check_interval(0)
+        g.step(warm, treatment)
+        times = sorted(timed_steps(g, steps, treatment, torch) for _ in range(runs))
+        ms = times[runs // 2]
+        out[name] = {"ms_per_step": round(ms, 5), "mlups": round(cells / ms / 1e3, 1),
+                     "steps_per_launch": 2 if (g.get_step_pairing()[0] and treatment != FD_RK2) else 1}
+        del g
+    return out
 
 
 def cpu_baseline(p, rho, T, treatment, seconds):
@@ -535,6 +563,8 @@ def main():
                                  "launch_ms": [round(kt[k], 5) for k in ("median", "min", "max")],
                                  "steps_per_launch": per_launch}
 
+    by_treatment = {} if args.no_extra else treatment_section(p, rho, T, args, torch)
+
     line = {
         "metric": "MLUPS (FP64 vs FP32-dev, % HBM roofline); wall-time to 1e-8 residual vs plain",
         "value": round(mlups, 1),
@@ -569,6 +599,7 @@ def main():
                                       if traffic else None),
                      "copy_GBs": round(copy_gbs, 1)},
         "by_precision": extra,
+        "by_treatment": by_treatment,
         "host_inclusive": host_inclusive,
     }
     if not args.no_jump:
