@@ -100,6 +100,21 @@ def test_wall_slab_2048_full_run(precision, treatment, fixed):
         assert 0.79 * Tc < col[3].min() and col[3].max() < 0.91 * Tc
     else:
         assert col[3].max() / col[3].min() > 3.0
+    # and across each interface, 8 rows into each phase: the corrected
+    # treatment keeps T continuous (the walls' gradient alone changes it by
+    # 0.1 Tc over 2048 rows, under 0.1 % across the 16 rows); the plain one
+    # drives rho T towards uniform (Eq. 23), so T_v/T_l heads for
+    # rho_l/rho_v (about 12.9) and far beyond the walls' ratio of 1.125
+    r, t = col[0], col[3]
+    mid = 0.5 * (r.min() + r.max())
+    for k in _crossings(r):
+        v, l = (k - 9, k + 8) if r[k] > mid else (k + 8, k - 9)
+        jump, dens = float(t[v] / t[l]), float(r[l] / r[v])
+        say("interface at row", k, "T_v/T_l", jump, "rho_l/rho_v", dens)
+        if treatment == CORRECTED:
+            assert abs(jump - 1.0) < 5e-3
+        else:
+            assert jump > 5.0 and jump < 1.2 * dens
 
 
 def _windows(n):
