@@ -527,10 +527,18 @@ hipError_t one_step(lbm_ctx *h, int treatment) {
     mo.ux = h->staging + n;
     mo.uy = h->staging + 2 * n;
     mo.T = h->staging + 3 * n;
-    hipError_t e = lbmdev::launch_moments(h->m, h->tm, h->st, h->buf[h->cur], mo, h->stream);
-    if (e != hipSuccess) return e;
-    e = lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], LBM_PLAIN,
-                            h->counters, h->stream);
+    hipError_t e;
+    if (h->p.wall_x != 2 && h->t.pf >= 2) {
+      // one launch steps f and writes the moments of time t; the
+      // finite-difference update then writes g whole
+      e = lbmdev::launch_step_fd(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], h->counters, mo,
+                                 h->stream);
+    } else {
+      e = lbmdev::launch_moments(h->m, h->tm, h->st, h->buf[h->cur], mo, h->stream);
+      if (e == hipSuccess)
+        e = lbmdev::launch_step(h->m, h->t, h->st, h->buf[h->cur], h->buf[1 - h->cur], LBM_PLAIN,
+                                h->counters, h->stream);
+    }
     if (e != hipSuccess) return e;
     return lbmdev::launch_fd(h->m, h->st, h->staging, h->fd, h->buf[1 - h->cur], h->stream);
   }

@@ -51,7 +51,11 @@ struct Model {
 // extra live values would push the row buffers into scratch memory)
 // MODE_STEP_SRC is MODE_STEP with the source term phi div u of Eq. (5) in
 // the g update, from velocity planes of time t passed in MomentsOut::ux, uy
-enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_OPEN = 2, MODE_STEP_SRC = 3 };
+// MODE_STEP_FD is the f half of MODE_STEP for the finite-difference
+// treatment: it also writes rho, u and T of time t (the moments a
+// MODE_MOMENTS launch would write) to MomentsOut::rho, ux, uy, T and
+// stores no g, which the finite-difference update then writes whole
+enum Mode { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_OPEN = 2, MODE_STEP_SRC = 3, MODE_STEP_FD = 4 };
 
 // Output/side buffers of a moments launch (all optional).
 struct MomentsOut {
@@ -85,6 +89,8 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
 // One step with the source term w_i phi div u of Eq. (5) added to the LB g
 // update, phi = -T (dp_EOS/dT)_rho; ux, uy: dense [ny][nx] velocity planes of
 // time t (the moments launch writes them).
+hipError_t launch_step_fd(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                          unsigned long long *cc, const MomentsOut &mo, hipStream_t s);
 hipError_t launch_step_src(const Model &m, const Tiling &t, int st, const void *src, void *dst,
                            int treatment, unsigned long long *clamp_counter, const double *ux,
                            const double *uy, hipStream_t s);

@@ -415,6 +415,15 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
     Fx += mm.rho * m.gx;
     Fy += mm.rho * m.gy;
 
+    if (MODE == MODE_STEP_FD && inner) {
+      // the moments of time t, as a MODE_MOMENTS launch writes them
+      const long long o = (long long)r * nx + x;
+      mo.rho[o] = mm.rho;
+      mo.ux[o] = ((double)mm.jx + 0.5 * Fx) / mm.rho;
+      mo.uy[o] = ((double)mm.jy + 0.5 * Fy) / mm.rho;
+      mo.T[o] = mm.E * m.inv_cv / mm.rho;
+    }
+
     if (MODE == MODE_MOMENTS) {
       const double ux = ((double)mm.jx + 0.5 * Fx) / mm.rho;
       const double uy = ((double)mm.jy + 0.5 * Fy) / mm.rho;
@@ -497,7 +506,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         const int row = ky[i] > 0 ? rU : (ky[i] < 0 ? rD : r);
         const unsigned cell = inner ? (unsigned)(row * pitch + col) : dummy;
         bst(db.f, cell * sz, (unsigned)i * pb, (S)fs);  // plane offset in the scalar operand
-        bst(db.g, cell * sz, (unsigned)i * pb, (S)gs);
+        if (MODE != MODE_STEP_FD) bst(db.g, cell * sz, (unsigned)i * pb, (S)gs);
       }
     } else {
 #pragma unroll
@@ -560,7 +569,7 @@ __device__ void tile(const Model &m, const void *__restrict__ src_v, void *__res
         const unsigned q = stays ? (unsigned)i : (unsigned)ko[i];
         const unsigned cell = !inner ? dummy : (stays ? (unsigned)(row * pitch + col) : own);
         bst(db.f, cell * sz + q * pb, 0u, (S)f_out);
-        bst(db.g, cell * sz + q * pb, 0u, (S)g_out);
+        if (MODE != MODE_STEP_FD) bst(db.g, cell * sz + q * pb, 0u, (S)g_out);
       }
     }
   };
@@ -1408,6 +1417,12 @@ hipError_t launch_step(const Model &m, const Tiling &t, int st, const void *src,
   }
   if (t.pf >= 2) return launch_tile_st<MODE_STEP, 2>(m, t, st, src, dst, treatment, cc, mo, s);
   return launch_tile_st<MODE_STEP, 1>(m, t, st, src, dst, treatment, cc, mo, s);
+}
+
+hipError_t launch_step_fd(const Model &m, const Tiling &t, int st, const void *src, void *dst,
+                          unsigned long long *cc, const MomentsOut &mo, hipStream_t s) {
+  if (!mo.rho || !mo.ux || !mo.uy || !mo.T || m.wall_x == 2 || t.pf < 2) return hipErrorInvalidValue;
+  return launch_tile_st<MODE_STEP_FD, 2>(m, t, st, src, dst, 0, cc, mo, s);
 }
 
 hipError_t launch_step_src(const Model &m, const Tiling &t, int st, const void *src, void *dst,
