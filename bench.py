@@ -466,8 +466,9 @@ def steady_section(count, torch, n=64, target=1e-8, cap=600000):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the slab would shard as y-slabs; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (a lattice would "
+              "shard as y-slabs exchanging three halo rows per two-step launch; batches would "
+              "split by lattice)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe_only(args.copy_probe)
