@@ -27,7 +27,8 @@ number of steps of the same workload, and again on one core
 (`single_core`, a child process with one OpenMP thread).  Side sections:
 `by_precision` (FP64 and FP32 global-shift storage on the same slab,
 timed like the roofline leg), `by_treatment` (the slab with each of the
-three temperature treatments), `interface_jump` (the slab's temperature
+three temperature treatments), `small_lattices` (64^2 and 256^2 droplets,
+latency-bound), `interface_jump` (the slab's temperature
 jump across its interfaces after 20,000 steps of each treatment, the
 forcing-term effect of Eq. (23)), `batched` (256 uneven lattices stepped
 together, autotuned, against the same lattices one at a time in the same
@@ -300,6 +301,33 @@ def treatment_section(p, rho, T, args, torch, warm=100, runs=5, steps=200):
     return out
 
 
+def small_section(torch, steps=2000, runs=3):
+    """Lattices too small to fill the device, which are bound by latency,
+    not HBM (a roofline fraction means nothing there): the 64^2 periodic
+    droplet for its 2000 steps with each treatment in FP64 (the two-treatment
+    parity workload), and a 256^2 droplet (the size of the warm-start
+    workload's boxes in the survey's recipe).  MLUPS from the median of
+    `runs` event-timed runs of `steps` steps."""
+    from paper_1405_2232_amd import inputs
+    from paper_1405_2232_amd.lbm import CORRECTED, PLAIN, Lattice
+    out = {}
+    for n, radius in ((64, 16.0), (256, 64.0)):
+        p, rho, T = inputs.static_droplet(nx=n, ny=n, radius=radius)
+        # the plain treatment with the EOS at T0, as in the parity workload
+        # (with the EOS at the local temperature it leaves the EOS domain)
+        for name, treatment, fixed in (("plain_eos_at_T0", PLAIN, True), ("corrected", CORRECTED, False)):
+            g = Lattice(dict(p, eos_fixed_T=fixed), "fp64")
+            g.init_fields(rho, T)
+            g.set_check_interval(0)
+            g.step(100, treatment)
+            ms = sorted(timed_steps(g, steps, treatment, torch) for _ in range(runs))[runs // 2]
+            out["droplet_%d_fp64_%s" % (n, name)] = {"us_per_step": round(ms * 1e3, 2),
+                                                      "mlups": round(n * n / ms / 1e3, 1),
+                                                      "two_step": g.get_step_pairing()[0]}
+            del g
+    return out
+
+
 def cpu_baseline(p, rho, T, treatment, seconds):
     """FP64 oracle on the host cores: time whole steps of the same workload
     until about `seconds` have passed."""
@@ -565,6 +593,7 @@ def main():
                                  "steps_per_launch": per_launch}
 
     by_treatment = {} if args.no_extra else treatment_section(p, rho, T, args, torch)
+    small = {} if args.no_extra else small_section(torch)
 
     line = {
         "metric": "MLUPS (FP64 vs FP32-dev, % HBM roofline); wall-time to 1e-8 residual vs plain",
@@ -601,6 +630,7 @@ def main():
                      "copy_GBs": round(copy_gbs, 1)},
         "by_precision": extra,
         "by_treatment": by_treatment,
+        "small_lattices": small,
         "host_inclusive": host_inclusive,
     }
     if not args.no_jump:
