@@ -211,3 +211,28 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_checkpoint_load_rejects_other_files_before_any_copy(tmp_path):
+    """lbm_load checks the file's header against the handle before it
+    touches the device: a file of another format, of another lattice size
+    or cut short is LBM_EINVAL (with no device here, a copy would have
+    failed with LBM_EDEVICE instead)."""
+    import struct
+    cfg = inputs.static_droplet(nx=32, ny=32, radius=8, seed=1)[0]
+    L, h = _host_handle(cfg, "fp32local")
+    try:
+        def header(magic=b"LBMCKPT2", nx=32, ny=32):
+            # magic, nx, ny, precision, cur, steps, clamps, bytes, plane, pitch, rpitch, rho_ref, cvT_ref
+            return struct.pack("<8s4iqQQqii2d", magic, nx, ny, 2, 0, 0, 0, 0, 0, 0, 0, 0.1, 0.08)
+        cases = {"other format": header(magic=b"LBMCKPT1") + b"\0" * 64,
+                 "other size": header(nx=64) + b"\0" * 64,
+                 "short header": header()[:20],
+                 "empty": b""}
+        for name, data in cases.items():
+            path = tmp_path / (name.replace(" ", "_") + ".ckpt")
+            path.write_bytes(data)
+            assert L.lbm_load(h, str(path).encode()) == lbm.EINVAL, name
+        assert L.lbm_load(h, str(tmp_path / "missing.ckpt").encode()) == lbm.EINVAL
+    finally:
+        L.lbm_destroy(h)
