@@ -1,7 +1,7 @@
 """Train the warm-start network on solver trajectories and evaluate it.
 
     python -m paper_1405_2232_amd.train_warmstart --out DIR [--physical]
-        [--stage all|train|eval] [--weights FILE]
+        [--stage all|train|eval] [--weights FILE] [--init-weights FILE]
 
 (defaults: 64 x 64 cases with 1-3 droplets, 1024 training solves to a
 1e-7 residual, 120 epochs, 64 held-out cases evaluated at 1e-8; with
@@ -55,6 +55,9 @@ def main(argv=None):
                          "multiple of the cold start's")
     ap.add_argument("--stage", choices=("all", "train", "eval"), default="all")
     ap.add_argument("--weights", default=None, help="trained parameters for --stage eval")
+    ap.add_argument("--init-weights", default=None,
+                    help="start training from these parameters (the network is convolutional, so "
+                         "parameters trained on one box size serve another) instead of a fresh init")
     args = ap.parse_args(argv)
 
     from paper_1405_2232_amd import inputs
@@ -84,7 +87,7 @@ def main(argv=None):
     gen_s = time.perf_counter() - t0
 
     # 2. training
-    ws = WarmStart(args.n)
+    ws = WarmStart(args.n, params=load_params(args.init_weights) if args.init_weights else None)
     data = ws.dataset([train_cases[i] for i in keep], steady)
     t0 = time.perf_counter()
     hist = ws.train(data, epochs=args.epochs, lr=args.lr, log=log)
@@ -96,7 +99,7 @@ def main(argv=None):
     res = {"n": args.n, "train_cases": args.train, "train_converged": len(keep),
            "train_target": args.train_target, "train_cap": args.train_cap, "max_drops": args.max_drops,
            "epochs": args.epochs, "loss": hist, "data_generation_s": round(gen_s, 1),
-           "training_s": round(train_s, 1), "physical": args.physical}
+           "training_s": round(train_s, 1), "physical": args.physical, "init_weights": args.init_weights}
     if args.stage == "train":
         with open(os.path.join(args.out, "warmstart_train.json"), "w") as fp:
             json.dump(res, fp, indent=1)
