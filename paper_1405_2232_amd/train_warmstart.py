@@ -139,7 +139,8 @@ def _evaluate(args, ws, test_cases, res, t_all):
                  "mean_steps_on_both": float(wsteps.mean()) if len(wsteps) else None},
         "step_ratio_warm_over_cold_on_both": float(wsteps.sum() / cs.sum()) if len(cs) else None,
         "unscreened": {"converged": int(sum(s is not None for s in raw["steps"])),
-                       "wall_s": round(raw["wall_s"], 2), "steps_capped_total": capped(raw["steps"])},
+                       "wall_s": round(raw["wall_s"], 2), "steps_capped_total": capped(raw["steps"]),
+                       "invalid_predictions": raw["invalid_inits"]},
         "cold_steps": cold["steps"], "warm_steps": warm["steps"], "unscreened_steps": raw["steps"],
         "predicted_residual": rp, "cold_residual": rc,
         "total_s": round(time.perf_counter() - t_all, 1),

@@ -17,7 +17,7 @@ import time
 
 import numpy as np
 
-from .lbm import CORRECTED, Batch
+from .lbm import CORRECTED, Batch, LbmError
 from .nn import UNet
 
 
@@ -36,18 +36,24 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
     `chunk` steps.  FP64 storage by default: with FP32 storage the one-step
     residual stalls between 1e-7 and 1e-6 (rounding of the stored
     distributions).  Returns a dict with per-case steps (None when the cap or
-    a non-finite value stopped it), the wall time, and (keep) the final
-    fields as FP64 host arrays.  `log` (a callable) gets a progress line
+    a non-finite value stopped it), the wall time, the number of given
+    initial states the library refused (those lattices start cold, e.g. a
+    prediction with a negative density), and (keep) the final fields as
+    FP64 host arrays.  `log` (a callable) gets a progress line
     every `log_every` steps."""
     import torch
     t0 = time.perf_counter()
     refs = [(float(r.mean()), float(t.mean())) for _, r, t in cases]
     b = Batch([c[0] for c in cases], precision, refs=refs)
+    fallback = 0
     for i, (m, (p, rho, T)) in enumerate(zip(b.members, cases)):
         if inits is not None and inits[i] is not None:
-            m.init_fields(*inits[i], physical=physical)
-        else:
-            m.init_fields(rho, T, physical=physical)
+            try:
+                m.init_fields(*inits[i], physical=physical)
+                continue
+            except LbmError:
+                fallback += 1  # not a valid state (e.g. a negative density): the cold start
+        m.init_fields(rho, T, physical=physical)
     if graph:
         b.use_graph(graph)
     n = len(cases)
@@ -73,7 +79,7 @@ def solve(cases, precision="fp64", inits=None, target=1e-8, cap=200000, chunk=10
                 done, sum(steps[i] is None and not failed[i] for i in range(n)), n, time.perf_counter() - t0))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = {"steps": steps, "failed": failed, "wall_s": wall, "cap": cap}
+    out = {"steps": steps, "failed": failed, "wall_s": wall, "cap": cap, "invalid_inits": fallback}
     if keep:
         fields = []
         for i in range(n):
